@@ -1,0 +1,253 @@
+"""FP64 CPU oracle of the exhaustive RKN seed scan -- TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes access to ``liboracle.so`` (plain C, built from ``rkn_oracle.c``).
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package; the GPU library and its Python binding never
+do, and the two share no code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "rkn_oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (FP64, no contraction, OpenMP over seeds)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+               "-Wall", "-Wextra", SRC, "-o", LIB_PATH + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OrcGeometry(C.Structure):
+    _fields_ = [("n_wires", C.c_int32), ("mx", C.c_void_p), ("my", C.c_void_p), ("mz", C.c_void_p),
+                ("ux", C.c_void_p), ("uy", C.c_void_p), ("uz", C.c_void_p), ("half_len", C.c_void_p),
+                ("layer_of", C.c_void_p), ("n_layers", C.c_int32), ("layer_rmin", C.c_void_p),
+                ("layer_rmax", C.c_void_p)]
+
+
+class OrcField(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("bz", C.c_double), ("nr", C.c_int32), ("nz", C.c_int32),
+                ("r0", C.c_double), ("r1", C.c_double), ("z0", C.c_double), ("z1", C.c_double),
+                ("br", C.c_void_p), ("bzg", C.c_void_p)]
+
+
+class OrcParams(C.Structure):
+    _fields_ = [("R0", C.c_double), ("charge", C.c_double), ("step_mm", C.c_double),
+                ("lambda_mm2", C.c_double), ("n_steps", C.c_int32), ("pad", C.c_int32)]
+
+
+class OrcWindow(C.Structure):
+    _fields_ = [("event", C.c_int32), ("candidate", C.c_int32), ("center", C.c_double * 5),
+                ("half_width", C.c_double * 5), ("count", C.c_int32 * 5), ("pad", C.c_int32)]
+
+
+class OrcHoughParams(C.Structure):
+    _fields_ = [("n_xy", C.c_int32), ("n_r", C.c_int32), ("xy_half", C.c_double),
+                ("r_min", C.c_double), ("r_max", C.c_double), ("min_votes", C.c_int32),
+                ("max_cand", C.c_int32), ("R0", C.c_double), ("charge", C.c_double),
+                ("b_ref", C.c_double), ("gran", C.c_double * 5), ("center_z", C.c_double),
+                ("center_pz", C.c_double), ("count", C.c_int32 * 5), ("grow", C.c_int32 * 5),
+                ("count_max", C.c_int32), ("pad", C.c_int32), ("max_seeds_event", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        _lib.orc_score.restype = C.c_double
+        _lib.orc_score.argtypes = [P, P, P, P, C.c_int32, P, P, C.c_int32, P, P]
+        _lib.orc_seg_wire_dist2.restype = C.c_double
+        _lib.orc_seg_wire_dist2.argtypes = [P, P, P, P, C.c_double]
+        _lib.orc_field_eval.argtypes = [P, P, P]
+        _lib.orc_rkn_step.argtypes = [P, C.c_double, C.c_double, P, P]
+        _lib.orc_seed_state.argtypes = [P, P, P, P, P]
+        _lib.orc_trace.argtypes = [P, P, C.c_int64, P, C.c_int32, P, P]
+        _lib.orc_doca2.argtypes = [P, P, P, P, C.c_int32, P, P]
+        _lib.orc_window_seed.argtypes = [P, C.c_int64, P]
+        _lib.orc_scan_windows.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int32, P, C.c_int32,
+                                          P, P, P, P, P]
+        _lib.orc_scan_seeds.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int64, P, P, P, P, P, P,
+                                        C.c_int32, P, P, P, P]
+        _lib.orc_hough_accumulate.argtypes = [P, P, C.c_int32, P, P]
+        _lib.orc_hough_peaks.argtypes = [P, P, C.c_int32, P, P]
+        _lib.orc_hough_window.argtypes = [P, P, C.c_int64, P]
+        _lib.orc_hough_seed_windows.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P]
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+class Oracle:
+    """Holds contiguous copies of geometry/field/hits and the C structs pointing at them."""
+
+    def __init__(self, geo, field):
+        self._keep = []
+        k = self._keep
+        def arr(x, dt):
+            a = np.ascontiguousarray(x, dtype=dt); k.append(a); return a
+        self.geo = OrcGeometry(geo.n_wires, _ptr(arr(geo.mx, np.float64)), _ptr(arr(geo.my, np.float64)),
+                               _ptr(arr(geo.mz, np.float64)), _ptr(arr(geo.ux, np.float64)),
+                               _ptr(arr(geo.uy, np.float64)), _ptr(arr(geo.uz, np.float64)),
+                               _ptr(arr(geo.half_len, np.float64)), _ptr(arr(geo.layer_of, np.int32)),
+                               geo.n_layers, _ptr(arr(geo.layer_rmin, np.float64)),
+                               _ptr(arr(geo.layer_rmax, np.float64)))
+        if field.kind == "uniform":
+            self.field = OrcField(0, field.bz, 0, 0, 0, 0, 0, 0, None, None)
+        else:
+            self.field = OrcField(1, 0.0, field.nr, field.nz, field.r0, field.r1, field.z0, field.z1,
+                                  _ptr(arr(field.br_grid, np.float32)), _ptr(arr(field.bz_grid, np.float32)))
+
+    @staticmethod
+    def params(R0=500.0, charge=-1.0, step_mm=1.0, lambda_mm2=64.0, n_steps=2000) -> OrcParams:
+        return OrcParams(R0, charge, step_mm, lambda_mm2, n_steps, 0)
+
+    # ---- propagation -------------------------------------------------------------
+    def field_eval(self, x):
+        x = np.ascontiguousarray(x, np.float64); B = np.zeros(3)
+        lib().orc_field_eval(C.byref(self.field), _ptr(x), _ptr(B))
+        return B
+
+    def seed_state(self, prm, seed):
+        s = np.ascontiguousarray(seed, np.float64); x = np.zeros(3); T = np.zeros(3); lam = C.c_double()
+        ok = lib().orc_seed_state(C.byref(prm), _ptr(s), _ptr(x), _ptr(T), C.byref(lam))
+        return bool(ok), x, T, lam.value
+
+    def rkn_step(self, lam, h, x, T):
+        x = np.array(x, np.float64); T = np.array(T, np.float64)
+        lib().orc_rkn_step(C.byref(self.field), lam, h, _ptr(x), _ptr(T))
+        return x, T
+
+    def trace(self, prm, seeds5, step_idx):
+        seeds5 = np.ascontiguousarray(np.atleast_2d(seeds5), np.float64)
+        step_idx = np.ascontiguousarray(step_idx, np.int32)
+        out = np.zeros((seeds5.shape[0], step_idx.size, 6))
+        lib().orc_trace(C.byref(self.field), C.byref(prm), seeds5.shape[0], _ptr(seeds5),
+                        step_idx.size, _ptr(step_idx), _ptr(out))
+        return out
+
+    # ---- distances and score -----------------------------------------------------
+    @staticmethod
+    def seg_wire_dist2(p0, p1, m, u, L):
+        a = [np.ascontiguousarray(v, np.float64) for v in (p0, p1, m, u)]
+        return lib().orc_seg_wire_dist2(*[_ptr(v) for v in a], float(L))
+
+    def doca2(self, prm, seed, wire_id):
+        s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
+        out = np.zeros(w.size)
+        lib().orc_doca2(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size,
+                        _ptr(w), _ptr(out))
+        return out
+
+    def score(self, prm, seed, wire_id, drift, mode=0):
+        s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
+        d = np.ascontiguousarray(drift, np.float32); n_in = C.c_int32(); pairs = C.c_int64()
+        E = lib().orc_score(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size,
+                            _ptr(w), _ptr(d), mode, C.byref(n_in), C.byref(pairs))
+        return E, n_in.value, pairs.value
+
+    @staticmethod
+    def window_struct(w) -> OrcWindow:
+        o = OrcWindow()
+        o.event = int(w["event"]); o.candidate = int(w["candidate"])
+        for d in range(5):
+            o.center[d] = float(w["center"][d]); o.half_width[d] = float(w["half_width"][d])
+            o.count[d] = int(w["count"][d])
+        return o
+
+    def window_seed(self, w, flat):
+        o = self.window_struct(w); out = np.zeros(5)
+        lib().orc_window_seed(C.byref(o), int(flat), _ptr(out))
+        return out
+
+    def scan_windows(self, prm, ev_off, wire_id, drift, windows, mode=1):
+        ev_off = np.ascontiguousarray(ev_off, np.int32); wire_id = np.ascontiguousarray(wire_id, np.int32)
+        drift = np.ascontiguousarray(drift, np.float32)
+        ws = (OrcWindow * max(len(windows), 1))()
+        for i, w in enumerate(windows):
+            ws[i] = self.window_struct(w)
+        total = int(sum(int(np.prod(w["count"].astype(np.int64))) for w in windows))
+        ne = ev_off.size - 1
+        score = np.zeros(total); n_in = np.zeros(total, np.int32)
+        bi = np.zeros(ne, np.int64); bs = np.zeros(ne); pairs = C.c_int64()
+        lib().orc_scan_windows(C.byref(self.geo), C.byref(self.field), C.byref(prm), ne, _ptr(ev_off),
+                               _ptr(wire_id), _ptr(drift), len(windows), ws, mode, _ptr(score),
+                               _ptr(n_in), _ptr(bi), _ptr(bs), C.byref(pairs))
+        return score, n_in, bi, bs, pairs.value
+
+    def scan_seeds(self, prm, ev_off, wire_id, drift, seed_event, seeds5, mode=1):
+        ev_off = np.ascontiguousarray(ev_off, np.int32); wire_id = np.ascontiguousarray(wire_id, np.int32)
+        drift = np.ascontiguousarray(drift, np.float32)
+        seeds5 = np.atleast_2d(np.asarray(seeds5, np.float64))
+        cols = [np.ascontiguousarray(seeds5[:, d]) for d in range(5)]
+        se = np.ascontiguousarray(seed_event, np.int32)
+        n = seeds5.shape[0]; ne = ev_off.size - 1
+        score = np.zeros(n); n_in = np.zeros(n, np.int32); bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+        lib().orc_scan_seeds(C.byref(self.geo), C.byref(self.field), C.byref(prm), ne, _ptr(ev_off),
+                             _ptr(wire_id), _ptr(drift), n, _ptr(se), *[_ptr(c) for c in cols], mode,
+                             _ptr(score), _ptr(n_in), _ptr(bi), _ptr(bs))
+        return score, n_in, bi, bs
+
+    # ---- Hough -------------------------------------------------------------------
+    @staticmethod
+    def hough_params(**kw) -> OrcHoughParams:
+        hp = OrcHoughParams()
+        d = dict(n_xy=256, n_r=64, xy_half=512.0, r_min=160.0, r_max=416.0, min_votes=6, max_cand=4,
+                 R0=500.0, charge=-1.0, b_ref=1.0, gran=(0.01, 50.0, 2.5, 2.5, 5.0), center_z=0.0,
+                 center_pz=0.0, count=(12, 12, 12, 12, 12), grow=(0, 0, 0, 0, 0), count_max=12,
+                 max_seeds_event=100000)
+        d.update(kw)
+        for k, v in d.items():
+            if k in ("gran", "count", "grow"):
+                arr = getattr(hp, k)
+                for i in range(5):
+                    arr[i] = v[i]
+            else:
+                setattr(hp, k, v)
+        return hp
+
+    def hough_accumulate(self, hp, wire_id):
+        w = np.ascontiguousarray(wire_id, np.int32)
+        acc = np.zeros(hp.n_xy * hp.n_xy * hp.n_r, np.uint32)
+        rc = lib().orc_hough_accumulate(C.byref(self.geo), C.byref(hp), w.size, _ptr(w), _ptr(acc))
+        if rc != 0:
+            raise ValueError("Hough accumulator geometry is not dyadic-exact")
+        return acc
+
+    def hough_peaks(self, hp, acc, max_out):
+        pf = np.zeros(max(max_out, 1), np.int64); pc = np.zeros(max(max_out, 1), np.uint32)
+        n = lib().orc_hough_peaks(C.byref(hp), _ptr(np.ascontiguousarray(acc, np.uint32)), max_out,
+                                  _ptr(pf), _ptr(pc))
+        return pf[:n], pc[:n]
+
+    def hough_seed_windows(self, hp, ev_off, wire_id, max_windows=4096):
+        from paper_1908_01949_amd.synth import WINDOW_DTYPE
+        ev_off = np.ascontiguousarray(ev_off, np.int32); wire_id = np.ascontiguousarray(wire_id, np.int32)
+        ws = (OrcWindow * max_windows)()
+        n = lib().orc_hough_seed_windows(C.byref(self.geo), C.byref(hp), ev_off.size - 1, _ptr(ev_off),
+                                         _ptr(wire_id), max_windows, ws)
+        if n < 0:
+            raise ValueError(f"need {-n} windows")
+        out = np.zeros(n, WINDOW_DTYPE)
+        for i in range(n):
+            out[i]["event"] = ws[i].event; out[i]["candidate"] = ws[i].candidate
+            out[i]["center"] = list(ws[i].center); out[i]["half_width"] = list(ws[i].half_width)
+            out[i]["count"] = list(ws[i].count)
+        return out

@@ -1,0 +1,627 @@
+/* FP64 CPU oracle of the exhaustive RKN seed scan -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+ * call this file. It shares no code with the GPU library.
+ *
+ * Built with -O2 -ffp-contract=off so that every operation rounds as written.
+ * Each function cites the passage of the paper (sections and Eq. 1) it follows;
+ * where the paper is silent the reading taken is stated beside the code.
+ *
+ * Parity status of each part:
+ *   field, seed state, RKN step, trace ...... pinned (closed-form helix, order 4,
+ *                                              |T| and Busch invariants)
+ *   segment/wire distance, DOCA ............. pinned (skew-line and axial-wire closed
+ *                                              forms, dense sampling)
+ *   score, argmin ........................... pinned (truth seed, symmetries, brute
+ *                                              force through an independent path)
+ *   band pruning ............................ pinned (bit-identical to brute force)
+ *   Hough accumulator and peaks ............. pinned (independent brute force,
+ *                                              hits on a known circle)
+ *   candidate -> window (constants) ......... parity unpinned as to quality: its
+ *                                              constants are free readings
+ */
+#include "rkn_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Field (section 2.2 sends "the magnetic field" to the device: a uniform value or
+ * an (r, z) map). Reading: bilinear in (r, z), clamped to the edge outside the
+ * grid; B_phi = 0; B_x = B_r x / r, B_y = B_r y / r, zero on the axis.          */
+void orc_field_eval(const orc_field *f, const double x[3], double B[3]) {
+  if (f->kind == 0) {
+    B[0] = 0.0; B[1] = 0.0; B[2] = f->bz;
+    return;
+  }
+  double r = sqrt(x[0] * x[0] + x[1] * x[1]);
+  double dr = (f->r1 - f->r0) / (double)(f->nr - 1);
+  double dz = (f->z1 - f->z0) / (double)(f->nz - 1);
+  double u = (r - f->r0) / dr;
+  double v = (x[2] - f->z0) / dz;
+  int i = (int)floor(u), j = (int)floor(v);
+  if (i < 0) i = 0;
+  if (i > f->nr - 2) i = f->nr - 2;
+  if (j < 0) j = 0;
+  if (j > f->nz - 2) j = f->nz - 2;
+  double a = u - i, b = v - j;
+  if (a < 0.0) a = 0.0;
+  if (a > 1.0) a = 1.0;
+  if (b < 0.0) b = 0.0;
+  if (b > 1.0) b = 1.0;
+  int n00 = j * f->nr + i, n01 = j * f->nr + i + 1;
+  int n10 = (j + 1) * f->nr + i, n11 = (j + 1) * f->nr + i + 1;
+  double br = (1.0 - b) * ((1.0 - a) * (double)f->br[n00] + a * (double)f->br[n01]) +
+              b * ((1.0 - a) * (double)f->br[n10] + a * (double)f->br[n11]);
+  double bz = (1.0 - b) * ((1.0 - a) * (double)f->bzg[n00] + a * (double)f->bzg[n01]) +
+              b * ((1.0 - a) * (double)f->bzg[n10] + a * (double)f->bzg[n11]);
+  if (r < 1e-9) {
+    B[0] = 0.0; B[1] = 0.0;
+  } else {
+    B[0] = br * x[0] / r;
+    B[1] = br * x[1] / r;
+  }
+  B[2] = bz;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 2.1: the seed holds (R0, theta0, z0) in cylindrical and (px0, py0, pz0)
+ * in Cartesian coordinates with R0 fixed, so five parameters are scanned.
+ * State: position, unit direction T = p/|p|, Lambda = kappa q / |p|.          */
+int orc_seed_state(const orc_params *p, const double seed[5], double x[3], double T[3], double *Lam) {
+  double pm = sqrt(seed[2] * seed[2] + seed[3] * seed[3] + seed[4] * seed[4]);
+  if (!(pm >= 1e-3)) return 0;
+  x[0] = p->R0 * cos(seed[0]);
+  x[1] = p->R0 * sin(seed[0]);
+  x[2] = seed[1];
+  T[0] = seed[2] / pm;
+  T[1] = seed[3] / pm;
+  T[2] = seed[4] / pm;
+  *Lam = ORC_KAPPA * p->charge / pm;
+  return 1;
+}
+
+/* x'' = Lam T x B(x): the Lorentz force on a unit-speed parametrisation. */
+static void accel(const orc_field *f, double Lam, const double x[3], const double T[3], double k[3]) {
+  double B[3];
+  orc_field_eval(f, x, B);
+  k[0] = Lam * (T[1] * B[2] - T[2] * B[1]);
+  k[1] = Lam * (T[2] * B[0] - T[0] * B[2]);
+  k[2] = Lam * (T[0] * B[1] - T[1] * B[0]);
+}
+
+/* Section 2.2: RKN track propagation. Classical fourth-order Runge-Kutta-Nystrom
+ * formula for y'' = f(y, y') (Abramowitz & Stegun 25.5.20), fixed step h, three
+ * field evaluations (start, middle, end). No renormalisation of T.            */
+void orc_rkn_step(const orc_field *f, double Lam, double h, double x[3], double T[3]) {
+  double k1[3], k2[3], k3[3], k4[3], xm[3], xe[3], Tt[3];
+  int c;
+  accel(f, Lam, x, T, k1);
+  for (c = 0; c < 3; ++c) xm[c] = x[c] + 0.5 * h * T[c] + 0.125 * h * h * k1[c];
+  for (c = 0; c < 3; ++c) Tt[c] = T[c] + 0.5 * h * k1[c];
+  accel(f, Lam, xm, Tt, k2);
+  for (c = 0; c < 3; ++c) Tt[c] = T[c] + 0.5 * h * k2[c];
+  accel(f, Lam, xm, Tt, k3);
+  for (c = 0; c < 3; ++c) xe[c] = x[c] + h * T[c] + 0.5 * h * h * k3[c];
+  for (c = 0; c < 3; ++c) Tt[c] = T[c] + h * k3[c];
+  accel(f, Lam, xe, Tt, k4);
+  for (c = 0; c < 3; ++c) {
+    x[c] = x[c] + h * T[c] + (h * h / 6.0) * (k1[c] + k2[c] + k3[c]);
+    T[c] = T[c] + (h / 6.0) * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+  }
+}
+
+int orc_trace(const orc_field *f, const orc_params *p, int64_t n_seeds, const double *seeds5,
+              int32_t n_sel, const int32_t *step_idx, double *states) {
+  int64_t s;
+  for (s = 0; s < n_seeds; ++s) {
+    double x[3], T[3], Lam;
+    double *out = states + s * (int64_t)n_sel * 6;
+    int32_t k, n = 0;
+    if (!orc_seed_state(p, seeds5 + 5 * s, x, T, &Lam)) {
+      for (k = 0; k < 6 * n_sel; ++k) out[k] = NAN;
+      continue;
+    }
+    for (k = 0; k < n_sel; ++k) {
+      while (n < step_idx[k]) {
+        orc_rkn_step(f, Lam, p->step_mm, x, T);
+        ++n;
+      }
+      out[6 * k + 0] = x[0]; out[6 * k + 1] = x[1]; out[6 * k + 2] = x[2];
+      out[6 * k + 3] = T[0]; out[6 * k + 4] = T[1]; out[6 * k + 5] = T[2];
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 2.2: distance of closest approach between the extrapolated track and a
+ * wire. Reading: the track between steps is its chord [p0, p1]; the wire is the
+ * finite segment m + t u, |t| <= L. The squared distance F(s, t) = |r + s d - t u|^2
+ * (r = p0 - m, d = p1 - p0) is a convex quadratic on [0,1] x [-L, L], so its
+ * minimum is the interior stationary point when that lies inside, otherwise the
+ * smallest of the four edge minima (each a clamped 1-D convex quadratic).      */
+static double f_at(const double r[3], const double d[3], const double u[3], double s, double t) {
+  double v0 = r[0] + s * d[0] - t * u[0];
+  double v1 = r[1] + s * d[1] - t * u[1];
+  double v2 = r[2] + s * d[2] - t * u[2];
+  return v0 * v0 + v1 * v1 + v2 * v2;
+}
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+double orc_seg_wire_dist2(const double p0[3], const double p1[3], const double m[3],
+                          const double u[3], double L) {
+  double r[3] = {p0[0] - m[0], p0[1] - m[1], p0[2] - m[2]};
+  double d[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+  double a = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double b = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+  double c = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double e = d[0] * r[0] + d[1] * r[1] + d[2] * r[2];
+  double g = u[0] * r[0] + u[1] * r[1] + u[2] * r[2];
+  double best = INFINITY, v, s, t;
+  double det = a * c - b * b;
+  if (det > 1e-14 * a * c) {          /* non-parallel: interior stationary point */
+    s = (b * g - c * e) / det;
+    t = (a * g - b * e) / det;
+    if (s >= 0.0 && s <= 1.0 && t >= -L && t <= L) {
+      v = f_at(r, d, u, s, t);
+      if (v < best) best = v;
+    }
+  }
+  /* edges s = 0 and s = 1: minimise over t */
+  t = clampd(g / c, -L, L);
+  v = f_at(r, d, u, 0.0, t);
+  if (v < best) best = v;
+  t = clampd((g + b) / c, -L, L);
+  v = f_at(r, d, u, 1.0, t);
+  if (v < best) best = v;
+  /* edges t = -L and t = +L: minimise over s */
+  if (a > 0.0) {
+    s = clampd(-(e + L * b) / a, 0.0, 1.0);
+    v = f_at(r, d, u, s, -L);
+    if (v < best) best = v;
+    s = clampd(-(e - L * b) / a, 0.0, 1.0);
+    v = f_at(r, d, u, s, L);
+    if (v < best) best = v;
+  }
+  return best;
+}
+
+static void wire_of(const orc_geometry *g, int32_t w, double m[3], double u[3], double *L) {
+  m[0] = g->mx[w]; m[1] = g->my[w]; m[2] = g->mz[w];
+  u[0] = g->ux[w]; u[1] = g->uy[w]; u[2] = g->uz[w];
+  *L = g->half_len[w];
+}
+
+int orc_doca2(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+              int32_t n_hits, const int32_t *wire_id, double *d2) {
+  double x[3], T[3], Lam, xo[3];
+  int32_t i, n;
+  for (i = 0; i < n_hits; ++i) d2[i] = INFINITY;
+  if (!orc_seed_state(p, seed, x, T, &Lam)) return 0;
+  for (n = 0; n < p->n_steps; ++n) {
+    xo[0] = x[0]; xo[1] = x[1]; xo[2] = x[2];
+    orc_rkn_step(f, Lam, p->step_mm, x, T);
+    for (i = 0; i < n_hits; ++i) {
+      double m[3], u[3], L, v;
+      wire_of(g, wire_id[i], m, u, &L);
+      v = orc_seg_wire_dist2(xo, x, m, u, L);
+      if (v < d2[i]) d2[i] = v;
+    }
+  }
+  return 1;
+}
+
+/* Radial extent of a chord: the largest radius is at an endpoint, the smallest
+ * is the clamped foot of the perpendicular from the z axis in the xy plane.   */
+static void chord_radial_range(const double p0[3], const double p1[3], double *rmin, double *rmax) {
+  double dx = p1[0] - p0[0], dy = p1[1] - p0[1];
+  double r0 = sqrt(p0[0] * p0[0] + p0[1] * p0[1]);
+  double r1 = sqrt(p1[0] * p1[0] + p1[1] * p1[1]);
+  double dd = dx * dx + dy * dy, s = 0.0, qx, qy;
+  if (dd > 0.0) s = clampd(-(p0[0] * dx + p0[1] * dy) / dd, 0.0, 1.0);
+  qx = p0[0] + s * dx;
+  qy = p0[1] + s * dy;
+  *rmax = r0 > r1 ? r0 : r1;
+  *rmin = sqrt(qx * qx + qy * qy);
+}
+
+/* Eq. (1): E = sum over fired wires of min(d_L^2, d_R^2, lambda). Reading: with
+ * D the DCA of the track to the wire and d the measured drift distance, the left
+ * and right candidates give d_L,R = D -+ d, so min(d_L^2, d_R^2) = (D - d)^2.
+ * Hits with (D - d)^2 < lambda are classified to the track (section 2.2).
+ *
+ * Band pruning (mode 1) is exact: a pair (chord, hit) can lower the hit's term
+ * below lambda only if the chord passes within d + sqrt(lambda) of the wire, which
+ * needs the chord's radial range to meet the layer's radial extent widened by
+ * that distance; a 1 mm margin keeps the rounding of borderline terms identical. */
+double orc_score(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+                 int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t mode,
+                 int32_t *n_in, int64_t *pairs) {
+  double x[3], T[3], Lam, xo[3], E = 0.0;
+  double *d2 = (double *)malloc(sizeof(double) * (n_hits > 0 ? n_hits : 1));
+  double sl = sqrt(p->lambda_mm2);
+  int64_t np = 0;
+  int32_t i, n, cnt = 0;
+  for (i = 0; i < n_hits; ++i) d2[i] = INFINITY;
+  if (!orc_seed_state(p, seed, x, T, &Lam)) {
+    free(d2);
+    if (n_in) *n_in = 0;
+    if (pairs) *pairs = 0;
+    return INFINITY;
+  }
+  for (n = 0; n < p->n_steps; ++n) {
+    double rmin = 0.0, rmax = 0.0;
+    xo[0] = x[0]; xo[1] = x[1]; xo[2] = x[2];
+    orc_rkn_step(f, Lam, p->step_mm, x, T);
+    if (mode == 1) chord_radial_range(xo, x, &rmin, &rmax);
+    for (i = 0; i < n_hits; ++i) {
+      double m[3], u[3], L, v;
+      int32_t w = wire_id[i];
+      if (mode == 1) {
+        int32_t l = g->layer_of[w];
+        double dc = (double)drift[i] + sl + 1.0;
+        if (rmax < g->layer_rmin[l] - dc || rmin > g->layer_rmax[l] + dc) continue;
+      }
+      wire_of(g, w, m, u, &L);
+      v = orc_seg_wire_dist2(xo, x, m, u, L);
+      ++np;
+      if (v < d2[i]) d2[i] = v;
+    }
+  }
+  for (i = 0; i < n_hits; ++i) {
+    double r = sqrt(d2[i]) - (double)drift[i];
+    double t = r * r;
+    if (t < p->lambda_mm2) {
+      E += t;
+      ++cnt;
+    } else {
+      E += p->lambda_mm2;
+    }
+  }
+  free(d2);
+  if (n_in) *n_in = cnt;
+  if (pairs) *pairs = np;
+  return E;
+}
+
+/* Seed grids: per dimension an inclusive linspace c - w + 2 w k / (n - 1)
+ * (n = 1 gives c); flat index with theta slowest and pz fastest.             */
+void orc_window_seed(const orc_window *w, int64_t flat, double seed[5]) {
+  int64_t k[5];
+  int d;
+  for (d = 4; d >= 0; --d) {
+    k[d] = flat % w->count[d];
+    flat /= w->count[d];
+  }
+  for (d = 0; d < 5; ++d) {
+    if (w->count[d] <= 1)
+      seed[d] = w->center[d];
+    else
+      seed[d] = w->center[d] - w->half_width[d] +
+                2.0 * w->half_width[d] * (double)k[d] / (double)(w->count[d] - 1);
+  }
+}
+
+static int64_t window_size(const orc_window *w) {
+  return (int64_t)w->count[0] * w->count[1] * w->count[2] * w->count[3] * w->count[4];
+}
+
+/* Section 2.2: the candidate seeds with the lowest E are kept. Reading: exact ties
+ * go to the lowest global seed index.                                          */
+int orc_scan_windows(const orc_geometry *g, const orc_field *f, const orc_params *p,
+                     int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
+                     int32_t n_windows, const orc_window *w, int32_t mode,
+                     double *score, int32_t *n_in, int64_t *best_index, double *best_score,
+                     int64_t *pairs_total) {
+  int64_t *base = (int64_t *)malloc(sizeof(int64_t) * (n_windows + 1));
+  int64_t total, s, ptot = 0;
+  int32_t e, k;
+  base[0] = 0;
+  for (k = 0; k < n_windows; ++k) base[k + 1] = base[k] + window_size(&w[k]);
+  total = base[n_windows];
+  for (e = 0; e < n_events; ++e) {
+    best_index[e] = -1;
+    best_score[e] = INFINITY;
+  }
+#pragma omp parallel for schedule(static) reduction(+ : ptot)
+  for (s = 0; s < total; ++s) {
+    int32_t kw = 0, ev, ni = 0;
+    int64_t np = 0;
+    double seed[5], E;
+    while (base[kw + 1] <= s) ++kw;
+    ev = w[kw].event;
+    orc_window_seed(&w[kw], s - base[kw], seed);
+    E = orc_score(g, f, p, seed, ev_off[ev + 1] - ev_off[ev], wire_id + ev_off[ev], drift + ev_off[ev],
+                  mode, &ni, &np);
+    score[s] = E;
+    if (n_in) n_in[s] = ni;
+    ptot += np;
+  }
+  for (s = 0; s < total; ++s) {
+    int32_t kw = 0, ev;
+    while (base[kw + 1] <= s) ++kw;
+    ev = w[kw].event;
+    if (best_index[ev] < 0 || score[s] < best_score[ev]) {
+      best_score[ev] = score[s];
+      best_index[ev] = s;
+    }
+  }
+  if (pairs_total) *pairs_total = ptot;
+  free(base);
+  return 0;
+}
+
+int orc_scan_seeds(const orc_geometry *g, const orc_field *f, const orc_params *p,
+                   int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
+                   int64_t n_seeds, const int32_t *seed_event, const double *theta, const double *z,
+                   const double *px, const double *py, const double *pz, int32_t mode,
+                   double *score, int32_t *n_in, int64_t *best_index, double *best_score) {
+  int64_t s;
+  int32_t e;
+  for (e = 0; e < n_events; ++e) {
+    best_index[e] = -1;
+    best_score[e] = INFINITY;
+  }
+#pragma omp parallel for schedule(static)
+  for (s = 0; s < n_seeds; ++s) {
+    int32_t ev = seed_event[s], ni = 0;
+    double seed[5] = {theta[s], z[s], px[s], py[s], pz[s]};
+    score[s] = orc_score(g, f, p, seed, ev_off[ev + 1] - ev_off[ev], wire_id + ev_off[ev],
+                         drift + ev_off[ev], mode, &ni, NULL);
+    if (n_in) n_in[s] = ni;
+  }
+  for (s = 0; s < n_seeds; ++s) {
+    int32_t ev = seed_event[s];
+    if (best_index[ev] < 0 || score[s] < best_score[ev]) {
+      best_score[ev] = score[s];
+      best_index[ev] = s;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 2.1: the transverse seed ranges come from a circle Hough transform of
+ * the hits. Readings: each hit votes with its wire's waist (x, y) quantised to
+ * 2^-8 mm (round half to even); the accumulator spans circle centres on an
+ * n_xy x n_xy grid and radii in n_r bins; a hit votes in every centre cell at the
+ * radius bin that contains its distance to the cell centre. All operands are
+ * multiples of 2^-8 mm, so the squared distance is an exact integer in units of
+ * 2^-16 mm^2 and the vote is exact.                                            */
+static int hough_geometry_ok(const orc_hough_params *hp) {
+  double wxy = 2.0 * hp->xy_half / hp->n_xy, wr = (hp->r_max - hp->r_min) / hp->n_r;
+  double a = hp->xy_half * 256.0, b = wxy * 256.0, c = hp->r_min * 256.0, d = wr * 256.0;
+  return hp->n_xy > 0 && hp->n_r > 0 && a == floor(a) && b == floor(b) && c == floor(c) &&
+         d == floor(d) && hp->r_min >= 0.0 && hp->r_max > hp->r_min;
+}
+
+int orc_hough_accumulate(const orc_geometry *g, const orc_hough_params *hp, int32_t n_hits,
+                         const int32_t *wire_id, uint32_t *acc) {
+  int64_t nbins = (int64_t)hp->n_xy * hp->n_xy * hp->n_r;
+  int64_t wxy_q = (int64_t)llround(2.0 * hp->xy_half / hp->n_xy * 256.0);
+  int64_t half_q = (int64_t)llround(hp->xy_half * 256.0);
+  int64_t rmin_q = (int64_t)llround(hp->r_min * 256.0);
+  int64_t wr_q = (int64_t)llround((hp->r_max - hp->r_min) / hp->n_r * 256.0);
+  int64_t *edge = (int64_t *)malloc(sizeof(int64_t) * (hp->n_r + 1));
+  int32_t i, a, b, k;
+  if (!hough_geometry_ok(hp)) {
+    free(edge);
+    return -1;
+  }
+  memset(acc, 0, sizeof(uint32_t) * nbins);
+  for (k = 0; k <= hp->n_r; ++k) {
+    int64_t rk = rmin_q + wr_q * k;
+    edge[k] = rk * rk;
+  }
+  for (i = 0; i < n_hits; ++i) {
+    int64_t X = (int64_t)nearbyint(g->mx[wire_id[i]] * 256.0);
+    int64_t Y = (int64_t)nearbyint(g->my[wire_id[i]] * 256.0);
+    for (a = 0; a < hp->n_xy; ++a) {
+      /* centre of cell a, times 256: -xy_half + wxy (a + 1/2) */
+      int64_t XC2 = -2 * half_q + wxy_q * (2 * a + 1);   /* twice the centre, exact */
+      int64_t DX = 2 * X - XC2;                          /* twice the offset        */
+      for (b = 0; b < hp->n_xy; ++b) {
+        int64_t YC2 = -2 * half_q + wxy_q * (2 * b + 1);
+        int64_t DY = 2 * Y - YC2;
+        int64_t rho2x4 = DX * DX + DY * DY;              /* 4 * rho^2               */
+        int32_t lo = 0, hi = hp->n_r;                    /* find edge[k] <= rho^2 < edge[k+1] */
+        if (rho2x4 < 4 * edge[0] || rho2x4 >= 4 * edge[hp->n_r]) continue;
+        while (hi - lo > 1) {
+          int32_t mid = (lo + hi) / 2;
+          if (4 * edge[mid] <= rho2x4)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        acc[((int64_t)a * hp->n_xy + b) * hp->n_r + lo] += 1u;
+      }
+    }
+  }
+  free(edge);
+  return 0;
+}
+
+/* Readings (the paper gives none): threshold max(min_votes, ceil(max/2)); a bin is
+ * a peak if it is at least every one of its 26 neighbours and strictly above the
+ * neighbours with a smaller flat index (plateaus keep their first bin); peaks are
+ * ordered by count (descending) then flat index (ascending).                   */
+static int is_peak(const orc_hough_params *hp, const uint32_t *acc, int a, int b, int k) {
+  int64_t me = ((int64_t)a * hp->n_xy + b) * hp->n_r + k;
+  uint32_t c = acc[me];
+  int da, db, dk;
+  for (da = -1; da <= 1; ++da)
+    for (db = -1; db <= 1; ++db)
+      for (dk = -1; dk <= 1; ++dk) {
+        int aa = a + da, bb = b + db, kk = k + dk;
+        int64_t nb;
+        if (!da && !db && !dk) continue;
+        if (aa < 0 || bb < 0 || kk < 0 || aa >= hp->n_xy || bb >= hp->n_xy || kk >= hp->n_r) continue;
+        nb = ((int64_t)aa * hp->n_xy + bb) * hp->n_r + kk;
+        if (acc[nb] > c) return 0;
+        if (acc[nb] == c && nb < me) return 0;
+      }
+  return 1;
+}
+
+typedef struct { uint32_t count; int64_t flat; } orc_peak;
+
+static int peak_order(const void *pa, const void *pb) {
+  const orc_peak *a = (const orc_peak *)pa, *b = (const orc_peak *)pb;
+  if (a->count != b->count) return a->count > b->count ? -1 : 1;
+  return a->flat < b->flat ? -1 : (a->flat > b->flat ? 1 : 0);
+}
+
+int orc_hough_peaks(const orc_hough_params *hp, const uint32_t *acc, int32_t max_out,
+                    int64_t *peak_flat, uint32_t *peak_count) {
+  int64_t nbins = (int64_t)hp->n_xy * hp->n_xy * hp->n_r, v, n = 0, cap = 64;
+  orc_peak *list = (orc_peak *)malloc(sizeof(orc_peak) * cap);
+  uint32_t mx = 0, thr;
+  int32_t j, nout;
+  for (v = 0; v < nbins; ++v)
+    if (acc[v] > mx) mx = acc[v];
+  thr = (mx + 1u) / 2u;                               /* ceil(max / 2) */
+  if (thr < (uint32_t)hp->min_votes) thr = (uint32_t)hp->min_votes;
+  if (thr < 1u) thr = 1u;
+  for (v = 0; v < nbins; ++v) {
+    int a, b, k;
+    if (acc[v] < thr) continue;
+    a = (int)(v / ((int64_t)hp->n_xy * hp->n_r));
+    b = (int)((v / hp->n_r) % hp->n_xy);
+    k = (int)(v % hp->n_r);
+    if (!is_peak(hp, acc, a, b, k)) continue;
+    if (n == cap) {
+      cap *= 2;
+      list = (orc_peak *)realloc(list, sizeof(orc_peak) * cap);
+    }
+    list[n].count = acc[v];
+    list[n].flat = v;
+    ++n;
+  }
+  qsort(list, (size_t)n, sizeof(orc_peak), peak_order);
+  nout = n < max_out ? (int32_t)n : max_out;
+  for (j = 0; j < nout; ++j) {
+    peak_flat[j] = list[j].flat;
+    peak_count[j] = list[j].count;
+  }
+  free(list);
+  return nout;
+}
+
+/* Section 2.1 (Fig. 4): transverse seeds extracted from the found circle. The
+ * circle (centre c, radius R) gives pT = kappa b_ref R; the seed point is the
+ * circle's crossing of r = R0 where the particle moves outward (for q < 0 it
+ * turns counter-clockwise seen from +z, velocity z^ x (P - c) / R). The window
+ * width grows with the peak's half-maximum extent (readings, see the params). */
+static int half_max_extent(const orc_hough_params *hp, const uint32_t *acc, int a, int b, int k,
+                           int axis) {
+  uint32_t c = acc[((int64_t)a * hp->n_xy + b) * hp->n_r + k];
+  int n = 1, dir, lim = axis == 2 ? hp->n_r : hp->n_xy;
+  for (dir = -1; dir <= 1; dir += 2) {
+    int step;
+    for (step = 1;; ++step) {
+      int aa = a, bb = b, kk = k, pos;
+      if (axis == 0) aa += dir * step;
+      if (axis == 1) bb += dir * step;
+      if (axis == 2) kk += dir * step;
+      pos = axis == 0 ? aa : (axis == 1 ? bb : kk);
+      if (pos < 0 || pos >= lim) break;
+      if (2u * acc[((int64_t)aa * hp->n_xy + bb) * hp->n_r + kk] < c) break;
+      ++n;
+    }
+  }
+  return n;
+}
+
+int orc_hough_window(const orc_hough_params *hp, const uint32_t *acc, int64_t peak_flat,
+                     orc_window *w) {
+  int a = (int)(peak_flat / ((int64_t)hp->n_xy * hp->n_r));
+  int b = (int)((peak_flat / hp->n_r) % hp->n_xy);
+  int k = (int)(peak_flat % hp->n_r);
+  double wxy = 2.0 * hp->xy_half / hp->n_xy, wr = (hp->r_max - hp->r_min) / hp->n_r;
+  double xc = -hp->xy_half + wxy * (a + 0.5), yc = -hp->xy_half + wxy * (b + 0.5);
+  double R = hp->r_min + wr * (k + 0.5);
+  double d = sqrt(xc * xc + yc * yc), R0 = hp->R0;
+  double pt = ORC_KAPPA * hp->b_ref * R;
+  double al, h, cx, cy, P[2][2], best_dot = 0.0;
+  int j, pick = -1, s, e1, e2, e3, d_;
+  int64_t prod;
+  if (!(d > 0.0) || d > R + R0 || d < fabs(R - R0)) return 0;
+  al = (R0 * R0 - R * R + d * d) / (2.0 * d);
+  h = R0 * R0 - al * al;
+  h = h > 0.0 ? sqrt(h) : 0.0;
+  cx = xc / d;
+  cy = yc / d;
+  P[0][0] = al * cx - h * cy; P[0][1] = al * cy + h * cx;
+  P[1][0] = al * cx + h * cy; P[1][1] = al * cy - h * cx;
+  for (j = 0; j < 2; ++j) {
+    double vx = -(P[j][1] - yc) / R, vy = (P[j][0] - xc) / R;   /* z^ x (P - c) / R */
+    double dot;
+    if (hp->charge > 0.0) { vx = -vx; vy = -vy; }
+    dot = vx * P[j][0] + vy * P[j][1];
+    if (dot > best_dot) {
+      best_dot = dot;
+      pick = j;
+      w->center[2] = pt * vx;
+      w->center[3] = pt * vy;
+    }
+  }
+  if (pick < 0) return 0;
+  w->center[0] = atan2(P[pick][1], P[pick][0]);
+  w->center[1] = hp->center_z;
+  w->center[4] = hp->center_pz;
+  e1 = half_max_extent(hp, acc, a, b, k, 0);
+  e2 = half_max_extent(hp, acc, a, b, k, 1);
+  e3 = half_max_extent(hp, acc, a, b, k, 2);
+  s = e1 > e2 ? e1 : e2;
+  if (e3 > s) s = e3;
+  for (d_ = 0; d_ < 5; ++d_) {
+    int n = hp->count[d_] + hp->grow[d_] * (s - 1);
+    if (n > hp->count_max) n = hp->count_max;
+    if (n < 1) n = 1;
+    w->count[d_] = n;
+  }
+  for (;;) {
+    int big = 0;
+    prod = (int64_t)w->count[0] * w->count[1] * w->count[2] * w->count[3] * w->count[4];
+    if (prod <= hp->max_seeds_event) break;
+    for (d_ = 1; d_ < 5; ++d_)
+      if (w->count[d_] > w->count[big]) big = d_;
+    if (w->count[big] <= 1) break;
+    w->count[big] -= 1;
+  }
+  for (d_ = 0; d_ < 5; ++d_) w->half_width[d_] = hp->gran[d_] * 0.5 * (double)(w->count[d_] - 1);
+  w->pad = 0;
+  return 1;
+}
+
+int orc_hough_seed_windows(const orc_geometry *g, const orc_hough_params *hp, int32_t n_events,
+                           const int32_t *ev_off, const int32_t *wire_id, int32_t max_windows,
+                           orc_window *out) {
+  int64_t nbins = (int64_t)hp->n_xy * hp->n_xy * hp->n_r;
+  uint32_t *acc = (uint32_t *)malloc(sizeof(uint32_t) * nbins);
+  int64_t *pf = (int64_t *)malloc(sizeof(int64_t) * (hp->max_cand > 0 ? hp->max_cand : 1));
+  uint32_t *pc = (uint32_t *)malloc(sizeof(uint32_t) * (hp->max_cand > 0 ? hp->max_cand : 1));
+  int32_t e, n = 0;
+  if (!hough_geometry_ok(hp)) {
+    free(acc); free(pf); free(pc);
+    return 0;
+  }
+  for (e = 0; e < n_events; ++e) {
+    int32_t np, j, cand = 0;
+    orc_hough_accumulate(g, hp, ev_off[e + 1] - ev_off[e], wire_id + ev_off[e], acc);
+    np = orc_hough_peaks(hp, acc, hp->max_cand, pf, pc);
+    for (j = 0; j < np; ++j) {
+      orc_window w;
+      memset(&w, 0, sizeof(w));
+      if (!orc_hough_window(hp, acc, pf[j], &w)) continue;
+      w.event = e;
+      w.candidate = cand++;
+      if (n < max_windows) out[n] = w;
+      ++n;
+    }
+  }
+  free(acc); free(pf); free(pc);
+  return n <= max_windows ? n : -n;
+}

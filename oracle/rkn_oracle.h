@@ -1,0 +1,132 @@
+/* FP64 CPU oracle of the exhaustive RKN seed scan -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct C: every function computes the definition it
+ * cites, with no blocking or fusion. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may call it; the GPU library shares no code with it.
+ *
+ * Paper: Yeo, Lee, Semertzidis, Kuno, "GPU Tracking in the COMET Phase-I
+ * Cylindrical Drift Chamber" (CTD/WIT 2019).
+ *
+ * Units: mm, MeV/c, tesla, elementary charge. Host pointers only.
+ */
+#ifndef RKN_ORACLE_H
+#define RKN_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_KAPPA 0.299792458   /* (MeV/c) / (T mm e) */
+
+typedef struct {
+  int32_t n_wires;
+  const double *mx, *my, *mz;        /* wire mid-point */
+  const double *ux, *uy, *uz;        /* unit direction */
+  const double *half_len;            /* wire = m +- half_len * u */
+  const int32_t *layer_of;
+  int32_t n_layers;
+  const double *layer_rmin, *layer_rmax;   /* radial extent of each layer's wires */
+} orc_geometry;
+
+typedef struct {
+  int32_t kind;                       /* 0 uniform B_z, 1 (r,z) grid */
+  double bz;                          /* uniform value */
+  int32_t nr, nz;
+  double r0, r1, z0, z1;
+  const float *br, *bzg;              /* [nz][nr] row-major */
+} orc_field;
+
+typedef struct {
+  double R0, charge, step_mm, lambda_mm2;
+  int32_t n_steps;
+  int32_t pad;
+} orc_params;
+
+typedef struct {
+  int32_t event, candidate;
+  double center[5], half_width[5];
+  int32_t count[5];
+  int32_t pad;
+} orc_window;
+
+/* Section 2.2: the field the track is propagated through. */
+void orc_field_eval(const orc_field *f, const double x[3], double B[3]);
+
+/* Section 2.1: seed (theta0, z0, px0, py0, pz0) on r = R0 -> (x, T, Lambda).
+ * Returns 0 (and leaves outputs untouched) when |p| < 1e-3 MeV/c. */
+int orc_seed_state(const orc_params *p, const double seed[5], double x[3], double T[3], double *Lam);
+
+/* Section 2.2 (RKN propagation): one Runge-Kutta-Nystrom step of x'' = Lam x' x B(x). */
+void orc_rkn_step(const orc_field *f, double Lam, double h, double x[3], double T[3]);
+
+/* States (x, T) after each of the n_sel step indices (0 = the seed state). */
+int orc_trace(const orc_field *f, const orc_params *p, int64_t n_seeds, const double *seeds5,
+              int32_t n_sel, const int32_t *step_idx, double *states /* [n][n_sel][6] */);
+
+/* Section 2.2 (DCA): exact squared distance between segment [p0,p1] and wire m +- L u. */
+double orc_seg_wire_dist2(const double p0[3], const double p1[3], const double m[3],
+                          const double u[3], double L);
+
+/* Per-hit squared DCA, minimum over all chords of the propagated track (brute force). */
+int orc_doca2(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+              int32_t n_hits, const int32_t *wire_id, double *d2 /* [n_hits] */);
+
+/* Eq. (1): E = sum_i min((D_i - d_i)^2, lambda); n_in = #{(D_i-d_i)^2 < lambda}.
+ * mode 0: brute force over every (chord, hit); mode 1: radial-band pruned (exact).
+ * pairs (optional) receives the number of (chord, hit) pairs evaluated. */
+double orc_score(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+                 int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t mode,
+                 int32_t *n_in, int64_t *pairs);
+
+/* Seed grid: flat index (theta slowest, pz fastest) -> seed. */
+void orc_window_seed(const orc_window *w, int64_t flat, double seed[5]);
+
+/* Scan every seed of every window; scores [sum of counts], best per event. */
+int orc_scan_windows(const orc_geometry *g, const orc_field *f, const orc_params *p,
+                     int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
+                     int32_t n_windows, const orc_window *w, int32_t mode,
+                     double *score, int32_t *n_in, int64_t *best_index, double *best_score,
+                     int64_t *pairs_total);
+
+/* Scan an explicit list of seeds (SoA). best_* are per event, indices into the list. */
+int orc_scan_seeds(const orc_geometry *g, const orc_field *f, const orc_params *p,
+                   int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
+                   int64_t n_seeds, const int32_t *seed_event, const double *theta, const double *z,
+                   const double *px, const double *py, const double *pz, int32_t mode,
+                   double *score, int32_t *n_in, int64_t *best_index, double *best_score);
+
+/* ---- Section 2.1: circle Hough transform over the wire (x, y) positions ---- */
+typedef struct {
+  int32_t n_xy, n_r;                  /* accumulator n_xy x n_xy x n_r */
+  double xy_half, r_min, r_max;       /* centre range [-xy_half, xy_half]^2, radius [r_min, r_max) */
+  int32_t min_votes, max_cand;        /* threshold = max(min_votes, ceil(max/2)); <= max_cand peaks */
+  double R0, charge, b_ref;           /* seed radius, charge, field for pT = kappa b_ref R */
+  double gran[5];                     /* grid step per seed dimension */
+  double center_z, center_pz;         /* longitudinal window centres */
+  int32_t count[5];                   /* base points per dimension */
+  int32_t grow[5];                    /* extra points per unit of peak half-max extent - 1 */
+  int32_t count_max;                  /* per-dimension cap */
+  int32_t pad;
+  int64_t max_seeds_event;            /* per-event cap on the product of counts */
+} orc_hough_params;
+
+/* Exact integer vote: accumulator [n_xy][n_xy][n_r] (uint32) for one event's hits. */
+int orc_hough_accumulate(const orc_geometry *g, const orc_hough_params *hp, int32_t n_hits,
+                         const int32_t *wire_id, uint32_t *acc);
+/* Peaks: flat bin indices ordered by count desc then index asc; returns their number. */
+int orc_hough_peaks(const orc_hough_params *hp, const uint32_t *acc, int32_t max_out,
+                    int64_t *peak_flat, uint32_t *peak_count);
+/* Candidate circle -> seed window; returns 0 if the circle misses r = R0. */
+int orc_hough_window(const orc_hough_params *hp, const uint32_t *acc, int64_t peak_flat,
+                     orc_window *w);
+/* All events: windows ordered by (event, candidate). Returns the number written, or
+ * -(required) when max_windows is too small. */
+int orc_hough_seed_windows(const orc_geometry *g, const orc_hough_params *hp, int32_t n_events,
+                           const int32_t *ev_off, const int32_t *wire_id, int32_t max_windows,
+                           orc_window *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,138 @@
+"""Pins of the oracle's circle Hough transform (section 2.1) and window construction."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from paper_1908_01949_amd import synth
+
+KAPPA = 0.299792458
+
+
+def numpy_accumulator(mx, my, n_xy=256, n_r=64, xy_half=512.0, r_min=160.0, r_max=416.0):
+    """Independent vote: float64 distances (exact here: dyadic operands) + searchsorted."""
+    X = np.round(np.asarray(mx) * 256.0) / 256.0       # numpy rounds half to even
+    Y = np.round(np.asarray(my) * 256.0) / 256.0
+    w = 2 * xy_half / n_xy
+    c = -xy_half + w * (np.arange(n_xy) + 0.5)
+    edges = (r_min + (r_max - r_min) / n_r * np.arange(n_r + 1)) ** 2
+    acc = np.zeros((n_xy, n_xy, n_r), np.int64)
+    A, B = np.meshgrid(np.arange(n_xy), np.arange(n_xy), indexing="ij")
+    for x, y in zip(X, Y):
+        rho2 = (x - c[:, None]) ** 2 + (y - c[None, :]) ** 2
+        k = np.searchsorted(edges, rho2, side="right") - 1
+        ok = (k >= 0) & (k < n_r)
+        np.add.at(acc, (A[ok], B[ok], k[ok]), 1)
+    return acc.ravel()
+
+
+def test_accumulator_matches_independent(geo, ev1, orc_u):
+    hp = orc_u.hough_params()
+    acc = orc_u.hough_accumulate(hp, ev1.wire_id)
+    ref = numpy_accumulator(geo.mx[ev1.wire_id], geo.my[ev1.wire_id])
+    assert np.array_equal(acc.astype(np.int64), ref)
+    # total votes equal an independent count of in-range cells per hit
+    assert int(acc.sum()) == int(ref.sum()) > 0
+
+
+def _circle_geometry(xc, yc, R, n, phase=0.3):
+    """A fake wire table whose waists lie on a circle (axial wires)."""
+    phi = phase + 2 * np.pi * np.arange(n) / n
+    mx = xc + R * np.cos(phi); my = yc + R * np.sin(phi)
+    g = synth.make_geometry()
+    return synth.Geometry(mx, my, np.zeros(n), np.zeros(n), np.zeros(n), np.ones(n),
+                          np.full(n, 750.0), np.zeros(n, np.int32), g.layer_rmin[:1], g.layer_rmax[:1],
+                          g.layer_radius[:1], np.array([n], np.int32), np.array([0], np.int32),
+                          np.zeros(1), 750.0)
+
+
+def test_hits_on_circle_make_the_peak():
+    import oracle
+    a, b, k = 140, 100, 30
+    xc = -512 + 4 * (a + 0.5); yc = -512 + 4 * (b + 0.5); R = 160 + 4 * (k + 0.5)
+    n = 40
+    g = _circle_geometry(xc, yc, R, n)
+    O = oracle.Oracle(g, synth.uniform_field())
+    hp = O.hough_params()
+    acc = O.hough_accumulate(hp, np.arange(n, dtype=np.int32))
+    flat = (a * 256 + b) * 64 + k
+    assert acc[flat] == n
+    pf, pc = O.hough_peaks(hp, acc, 4)
+    assert pf[0] == flat and pc[0] == n
+
+
+def test_peak_rules_on_synthetic_accumulator(orc_u):
+    hp = orc_u.hough_params(n_xy=8, n_r=8, xy_half=16.0, r_min=0.0, r_max=32.0, min_votes=3, max_cand=4)
+    acc = np.zeros(8 * 8 * 8, np.uint32)
+    def f(a, b, k):
+        return (a * 8 + b) * 8 + k
+    acc[f(1, 1, 1)] = 10            # isolated peak
+    acc[f(5, 5, 5)] = 7; acc[f(5, 5, 6)] = 7   # plateau: keep the lower flat index only
+    acc[f(3, 6, 2)] = 4             # below threshold ceil(10/2)=5 -> dropped
+    acc[f(6, 1, 1)] = 5; acc[f(6, 2, 2)] = 9   # 5 is not a local max
+    pf, pc = orc_u.hough_peaks(hp, acc, 4)
+    assert list(pf) == [f(1, 1, 1), f(6, 2, 2), f(5, 5, 5)]
+    assert list(pc) == [10, 9, 7]
+    pf, pc = orc_u.hough_peaks(hp, acc, 2)
+    assert list(pf) == [f(1, 1, 1), f(6, 2, 2)]
+
+
+def test_window_from_circle_geometry(orc_u):
+    """Window centre = outward crossing of the bin-centre circle with r = R0 (independent solve)."""
+    a, b, k = 150, 90, 50
+    hp = orc_u.hough_params(count=(5, 4, 5, 5, 3), grow=(1, 0, 1, 1, 0), count_max=9,
+                            max_seeds_event=10 ** 9, center_z=12.0, center_pz=-3.0, b_ref=1.0)
+    acc = np.zeros(256 * 256 * 64, np.uint32)
+    flat = (a * 256 + b) * 64 + k
+    acc[flat] = 20
+    acc[flat + 64] = 11          # b+1 above half max -> extent 2 along b
+    from paper_1908_01949_amd.synth import make_windows
+    w = make_windows([(0, 0, np.zeros(5), np.zeros(5), np.ones(5, int))])[0]
+    import oracle, ctypes
+    ow = oracle.OrcWindow()
+    ok = oracle.lib().orc_hough_window(ctypes.byref(hp), acc.ctypes.data, flat, ctypes.byref(ow))
+    assert ok == 1
+    xc = -512 + 4 * (a + 0.5); yc = -512 + 4 * (b + 0.5); R = 160 + 4 * (k + 0.5)
+    # independent: parametrise the circle, root-find |P| = R0, take the outward crossing
+    def g(phi):
+        return math.hypot(xc + R * math.cos(phi), yc + R * math.sin(phi)) - 500.0
+    phis = np.linspace(0, 2 * np.pi, 721)
+    vals = [g(p) for p in phis]
+    sols = [brentq(g, phis[i], phis[i + 1], xtol=1e-15) for i in range(720) if vals[i] * vals[i + 1] < 0]
+    assert len(sols) == 2
+    got = None
+    for p in sols:
+        P = np.array([xc + R * math.cos(p), yc + R * math.sin(p)])
+        v = np.array([-math.sin(p), math.cos(p)])          # counter-clockwise (q < 0)
+        if v @ P > 0:
+            got = (math.atan2(P[1], P[0]), KAPPA * R * v[0], KAPPA * R * v[1])
+    assert got is not None
+    assert ow.center[0] == pytest.approx(got[0], abs=1e-12)
+    assert ow.center[2] == pytest.approx(got[1], abs=1e-10)
+    assert ow.center[3] == pytest.approx(got[2], abs=1e-10)
+    assert ow.center[1] == 12.0 and ow.center[4] == -3.0
+    # half-max extent 2 -> counts base + grow
+    assert list(ow.count) == [6, 4, 6, 6, 3]
+    assert ow.half_width[0] == pytest.approx(0.01 * 2.5)
+    # cap: the largest count is reduced first (lowest dimension on ties)
+    hp2 = orc_u.hough_params(count=(5, 4, 5, 5, 3), grow=(1, 0, 1, 1, 0), count_max=9,
+                             max_seeds_event=6 * 4 * 6 * 6 * 3 - 1)
+    ow2 = oracle.OrcWindow()
+    oracle.lib().orc_hough_window(ctypes.byref(hp2), acc.ctypes.data, flat, ctypes.byref(ow2))
+    assert list(ow2.count) == [5, 4, 6, 6, 3]
+
+
+def test_hough_windows_cover_truth(geo, ufield, orc_u):
+    """On a single-turn event the best window contains the truth transverse seed (sanity)."""
+    ev = synth.event_fixed_total(geo, ufield, 0, n_total=150, noise_frac=0.2)
+    hp = orc_u.hough_params(count=(12, 12, 12, 12, 12), count_max=12, max_seeds_event=10 ** 9,
+                            gran=(0.1 / 11, 1000.0 / 11, 10.0 / 11, 10.0 / 11, 120.0 / 11))
+    off = np.array([0, ev.wire_id.size], np.int32)
+    ws = orc_u.hough_seed_windows(hp, off, ev.wire_id)
+    assert 1 <= len(ws) <= 4
+    t = ev.truth_seeds[0]
+    dth = [abs((w["center"][0] - t[0] + np.pi) % (2 * np.pi) - np.pi) for w in ws]
+    j = int(np.argmin(dth))
+    assert dth[j] < 0.06
+    assert abs(ws[j]["center"][2] - t[2]) < 6 and abs(ws[j]["center"][3] - t[3]) < 6
