@@ -1,0 +1,192 @@
+/* rknscan: exhaustive Runge-Kutta-Nystrom seed scan for drift-chamber track finding
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yeo, Lee, Semertzidis, Kuno, "GPU Tracking in the COMET Phase-I
+ * Cylindrical Drift Chamber" (CTD/WIT 2019). Every candidate seed
+ * (theta0, z0, px0, py0, pz0) on the cylinder r = R0 is propagated with a fixed-step
+ * RKN integrator of the Lorentz force (section 2.2), its distance of closest
+ * approach (DCA) to every fired wire is compared with the measured drift distance,
+ * and the seed is scored by E of Eq. (1); the lowest-E seed of each event is kept.
+ * A circle Hough transform over the hit wires narrows the seed windows (section 2.1).
+ *
+ * Conventions (all entry points):
+ *  - Units: mm, MeV/c, tesla, elementary charge (electrons: charge = -1).
+ *  - Status: every call returns rkn_status; 0 is success. On error nothing is
+ *    written to the outputs and rkn_last_error() describes the failure. All
+ *    arguments are validated before any device work. No exception crosses the ABI.
+ *  - Ownership: inputs are caller-owned and copied (uploads) or read during the
+ *    call; outputs are caller-owned. The context owns every device copy, its stream
+ *    (if it created one), work buffers and captured graphs.
+ *  - Pointers: input arrays of upload calls are host pointers. Output arrays are
+ *    host pointers unless rkn_scan_params.ptr_flags has RKN_PTR_DEVICE, in which
+ *    case they are device pointers on the context's device and the call is
+ *    stream-ordered (it returns without waiting). Host outputs make the call
+ *    synchronous.
+ *  - Threads: one context per host thread; calls on one context are serialised
+ *    by the caller.
+ */
+#ifndef RKNSCAN_H
+#define RKNSCAN_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rkn_status;
+#define RKN_OK 0
+#define RKN_E_ARG (-1)          /* invalid argument (NULL, size, NaN, out of range)   */
+#define RKN_E_STATE (-2)        /* missing upload or wrong call order                   */
+#define RKN_E_NOMEM (-3)        /* device allocation failed                             */
+#define RKN_E_DEVICE (-4)       /* HIP runtime error (text from hipGetErrorString)      */
+#define RKN_E_CAPACITY (-5)     /* output capacity too small; required size reported    */
+#define RKN_E_UNSUPPORTED (-6)  /* valid but unsupported configuration                  */
+
+#define RKN_PTR_DEVICE 1        /* rkn_scan_params.ptr_flags: outputs are device pointers */
+
+#define RKN_MAX_HITS_PER_EVENT 512
+#define RKN_MAX_LAYERS 64
+
+typedef struct rkn_ctx rkn_ctx;
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to run on,
+ * or NULL for a context-owned stream. */
+rkn_status rkn_create(int32_t device, void *hip_stream, rkn_ctx **out);
+/* Release every device resource of the context. NULL-safe. */
+void rkn_destroy(rkn_ctx *ctx);
+/* Text of the last error on this context; valid until the next call on it. */
+const char *rkn_last_error(const rkn_ctx *ctx);
+/* Wait for all work queued by the context. */
+rkn_status rkn_synchronize(rkn_ctx *ctx);
+/* Library version string. */
+const char *rkn_version(void);
+
+/* ---- Uploads (section 2.2: the field, hits and seeds are moved to GPU memory
+ *      before the scan) ---------------------------------------------------------- */
+
+/* Wire table: wire i is the segment m_i + t u_i, |t| <= half_len_i (u unit), in
+ * layer layer_of[i] (0 <= layer_of < n_layers <= RKN_MAX_LAYERS). layer_rmin/rmax
+ * bound the radial extent of each layer's wires and must be non-decreasing in the
+ * layer index (RKN_E_UNSUPPORTED otherwise). Replaces any previous geometry and
+ * invalidates uploaded hits. */
+rkn_status rkn_upload_geometry(rkn_ctx *ctx, int32_t n_wires,
+                               const double *mx, const double *my, const double *mz,
+                               const double *ux, const double *uy, const double *uz,
+                               const double *half_len, const int32_t *layer_of,
+                               int32_t n_layers, const double *layer_rmin,
+                               const double *layer_rmax);
+
+/* Uniform solenoid field B = (0, 0, bz_tesla). */
+rkn_status rkn_upload_field_uniform(rkn_ctx *ctx, double bz_tesla);
+
+/* Axisymmetric field map: B_r and B_z on nodes r_i = r0 + (r1-r0) i/(nr-1),
+ * z_j = z0 + (z1-z0) j/(nz-1), arrays [nz][nr] row-major, FP32 tesla. Evaluated by
+ * bilinear interpolation in (r, z), clamped to the edge outside the grid;
+ * B_x = B_r x/r, B_y = B_r y/r (0 on the axis). nr, nz >= 2. */
+rkn_status rkn_upload_field_rz(rkn_ctx *ctx, int32_t nr, int32_t nz, double r0, double r1,
+                               double z0, double z1, const float *br, const float *bz);
+
+/* Hits of n_events events in CSR form: event e owns hits ev_off[e] .. ev_off[e+1]-1
+ * (ev_off[0] = 0, non-decreasing, at most RKN_MAX_HITS_PER_EVENT per event);
+ * wire_id indexes the uploaded wire table; drift_mm is the measured drift distance
+ * (finite, >= 0). Requires the geometry. */
+rkn_status rkn_upload_hits(rkn_ctx *ctx, int32_t n_events, const int32_t *ev_off,
+                           const int32_t *wire_id, const float *drift_mm);
+
+/* ---- Seed windows ------------------------------------------------------------------ */
+
+/* A 5-D seed grid: per dimension d (theta [rad], z0 [mm], px, py, pz [MeV/c]) an
+ * inclusive linspace center-hw .. center+hw of count[d] points (count 1 -> center).
+ * Flat index: theta slowest, pz fastest. The global index of a seed is the sum of
+ * the sizes of the preceding windows plus its flat index. Windows are grouped by
+ * event in non-decreasing event order. */
+typedef struct {
+  int32_t event, candidate;
+  double center[5], half_width[5];
+  int32_t count[5];
+  int32_t pad;
+} rkn_window;
+
+/* Circle Hough transform (section 2.1) and the window built from each peak.
+ * Accumulator n_xy x n_xy centre cells over [-xy_half, xy_half]^2 and n_r radius
+ * bins over [r_min, r_max); every hit votes with its wire's mid-point (x, y),
+ * quantised to 2^-8 mm (half to even), in every centre cell at the radius bin
+ * holding its distance to the cell centre. The vote is exact integer arithmetic;
+ * xy_half, 2 xy_half/n_xy, r_min and (r_max-r_min)/n_r must be multiples of 2^-8 mm.
+ * Peaks: counts >= max(min_votes, ceil(max/2)), >= all 26 neighbours and > the
+ * neighbours with a smaller flat index; up to max_cand per event ordered by count
+ * desc, then flat index asc. A peak (bin centre xc, yc, R) gives pT = kappa b_ref R
+ * and the seed point where the circle crosses r = R0 moving outward (q < 0 turns
+ * counter-clockwise seen from +z); peaks whose circle misses r = R0 are dropped.
+ * Window: centre (theta0, center_z, px0, py0, center_pz); count[d] + grow[d] (s-1)
+ * points capped at count_max, s = the largest half-maximum extent of the peak along
+ * its three axes (in bins); while the product exceeds max_seeds_window (a cap per
+ * window) the largest
+ * count (lowest dimension on ties) is decremented; half width gran[d] (count-1)/2. */
+typedef struct {
+  int32_t n_xy, n_r;
+  double xy_half, r_min, r_max;
+  int32_t min_votes, max_cand;
+  double R0, charge, b_ref;
+  double gran[5];
+  double center_z, center_pz;
+  int32_t count[5];
+  int32_t grow[5];
+  int32_t count_max;
+  int32_t pad;
+  int64_t max_seeds_window;
+} rkn_hough_params;
+
+/* Run the Hough stage on every uploaded event; write up to max_windows windows to
+ * the host array `out` ordered by (event, candidate) and their number to *n_out.
+ * If more are needed, returns RKN_E_CAPACITY with *n_out = the required count. */
+rkn_status rkn_hough_seed_windows(rkn_ctx *ctx, const rkn_hough_params *hp, int32_t max_windows,
+                                  rkn_window *out, int32_t *n_out);
+
+/* Accumulator of one event (uint32 [n_xy][n_xy][n_r], host or device per ptr_flags);
+ * exposed so the integer vote can be checked bit for bit. */
+rkn_status rkn_hough_accumulator(rkn_ctx *ctx, const rkn_hough_params *hp, int32_t event,
+                                 int32_t ptr_flags, uint32_t *acc);
+
+/* ---- The scan (section 2.2, Eq. 1) ------------------------------------------------- */
+
+typedef struct {
+  double R0;          /* seed cylinder radius, mm (the paper fixes 500)            */
+  double charge;      /* particle charge, e                                        */
+  double step_mm;     /* RKN step h > 0                                            */
+  double lambda_mm2;  /* cutoff lambda >= 0 of Eq. (1)                             */
+  int32_t n_steps;    /* fixed number of RKN steps per seed, >= 1                  */
+  int32_t precision;  /* 32: FP32 propagation and distances, FP64 score; 64: FP64  */
+  int32_t ptr_flags;  /* RKN_PTR_DEVICE: outputs are device pointers               */
+  int32_t block_steps;/* steps per DCA block (0 = default); tuning knob            */
+} rkn_scan_params;
+
+/* Score every seed of the windows: E = sum over the event's hits of
+ * min((D - d)^2, lambda), D = minimum over the chords of the n_steps RKN steps of
+ * the exact chord/wire distance, d = drift (left/right ambiguity: min(d_L^2, d_R^2)
+ * = (D - d)^2). n_in[s] = #{hits with (D - d)^2 < lambda} (the classification rule
+ * of section 2.2). A seed with |p| < 1e-3 MeV/c scores +inf. score/n_in: arrays of
+ * the total seed count, or NULL to skip. best_index/best_score: per uploaded event,
+ * the lowest E and its global seed index (ties: lowest index; -1 / +inf when the
+ * event has no seed). */
+rkn_status rkn_scan_windows(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_windows,
+                            const rkn_window *w, double *score, int32_t *n_in,
+                            int64_t *best_index, double *best_score);
+
+/* Same score for an explicit seed list (SoA, host arrays, FP64). best_index is the
+ * position in the list. */
+rkn_status rkn_scan_seeds(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds,
+                          const int32_t *seed_event, const double *theta, const double *z,
+                          const double *px, const double *py, const double *pz,
+                          double *score, int32_t *n_in, int64_t *best_index, double *best_score);
+
+/* Propagated states: for each seed (host [n_seeds][5]) and each of the n_sel
+ * non-decreasing step indices (0 = the seed state), write (x, y, z, Tx, Ty, Tz) to
+ * states [n_seeds][n_sel][6] (FP64; the FP32 path is widened). */
+rkn_status rkn_trace(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, const double *seeds5,
+                     int32_t n_sel, const int32_t *step_idx, double *states);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -57,7 +57,7 @@ class OrcHoughParams(C.Structure):
                 ("max_cand", C.c_int32), ("R0", C.c_double), ("charge", C.c_double),
                 ("b_ref", C.c_double), ("gran", C.c_double * 5), ("center_z", C.c_double),
                 ("center_pz", C.c_double), ("count", C.c_int32 * 5), ("grow", C.c_int32 * 5),
-                ("count_max", C.c_int32), ("pad", C.c_int32), ("max_seeds_event", C.c_int64)]
+                ("count_max", C.c_int32), ("pad", C.c_int32), ("max_seeds_window", C.c_int64)]
 
 
 _lib = None
@@ -212,7 +212,7 @@ class Oracle:
         d = dict(n_xy=256, n_r=64, xy_half=512.0, r_min=160.0, r_max=416.0, min_votes=6, max_cand=4,
                  R0=500.0, charge=-1.0, b_ref=1.0, gran=(0.01, 50.0, 2.5, 2.5, 5.0), center_z=0.0,
                  center_pz=0.0, count=(12, 12, 12, 12, 12), grow=(0, 0, 0, 0, 0), count_max=12,
-                 max_seeds_event=100000)
+                 max_seeds_window=100000)
         d.update(kw)
         for k, v in d.items():
             if k in ("gran", "count", "grow"):

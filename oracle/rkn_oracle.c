@@ -585,7 +585,7 @@ int orc_hough_window(const orc_hough_params *hp, const uint32_t *acc, int64_t pe
   for (;;) {
     int big = 0;
     prod = (int64_t)w->count[0] * w->count[1] * w->count[2] * w->count[3] * w->count[4];
-    if (prod <= hp->max_seeds_event) break;
+    if (prod <= hp->max_seeds_window) break;
     for (d_ = 1; d_ < 5; ++d_)
       if (w->count[d_] > w->count[big]) big = d_;
     if (w->count[big] <= 1) break;

@@ -108,7 +108,7 @@ typedef struct {
   int32_t grow[5];                    /* extra points per unit of peak half-max extent - 1 */
   int32_t count_max;                  /* per-dimension cap */
   int32_t pad;
-  int64_t max_seeds_event;            /* per-event cap on the product of counts */
+  int64_t max_seeds_window;           /* per-window cap on the product of counts */
 } orc_hough_params;
 
 /* Exact integer vote: accumulator [n_xy][n_xy][n_r] (uint32) for one event's hits. */

@@ -1,0 +1,226 @@
+// Device-side arithmetic of the seed scan for gfx950: field evaluation, one RKN
+// step, the exact chord/wire distance, and wave-level helpers.
+//
+// Method (Yeo et al., CTD/WIT 2019, section 2.2): tracks are propagated with a
+// fixed-step Runge-Kutta-Nystrom integrator of the Lorentz force and compared
+// with the wires by their distance of closest approach.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rkn {
+
+constexpr double kKappa = 0.299792458;  // (MeV/c) / (T mm e)
+
+// Hit record staged per event, ordered by layer: wire segment m +- L u and drift.
+template <typename R>
+struct alignas(sizeof(R) * 8) HitRec {
+  R mx, my, mz, ux, uy, uz, L, drift;
+};
+
+// Wave-uniform read of a hit record through the constant address space, so the
+// compiler issues scalar loads (the records are read-only while a scan runs).
+template <typename R>
+__device__ __forceinline__ HitRec<R> load_hit_uniform(const HitRec<R>* p, int h) {
+  const __attribute__((address_space(4))) HitRec<R>* q =
+      (const __attribute__((address_space(4))) HitRec<R>*)p;
+  HitRec<R> w;
+  w.mx = q[h].mx;
+  w.my = q[h].my;
+  w.mz = q[h].mz;
+  w.ux = q[h].ux;
+  w.uy = q[h].uy;
+  w.uz = q[h].uz;
+  w.L = q[h].L;
+  w.drift = q[h].drift;
+  return w;
+}
+
+// Axisymmetric field: uniform B_z, or FP32 (B_r, B_z) nodes interleaved [nz][nr].
+struct FieldDev {
+  const float2* nodes;
+  int nr, nz;
+  double r0, z0, inv_dr, inv_dz;
+  double bz;
+};
+
+template <typename R>
+__device__ __forceinline__ R clampv(R v, R lo, R hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Bilinear (r, z) interpolation clamped to the grid edge; B_x,y = B_r (x, y)/r.
+template <typename R>
+__device__ __forceinline__ void field_rz(const FieldDev& f, R x, R y, R z, R& bx, R& by, R& bz) {
+  const R r = sqrt(x * x + y * y);
+  R u = (r - (R)f.r0) * (R)f.inv_dr;
+  R v = (z - (R)f.z0) * (R)f.inv_dz;
+  u = clampv(u, (R)0, (R)(f.nr - 1));
+  v = clampv(v, (R)0, (R)(f.nz - 1));
+  int i = (int)floor(u), j = (int)floor(v);
+  i = i > f.nr - 2 ? f.nr - 2 : i;
+  j = j > f.nz - 2 ? f.nz - 2 : j;
+  const R a = clampv(u - (R)i, (R)0, (R)1);
+  const R b = clampv(v - (R)j, (R)0, (R)1);
+  const float2* row0 = f.nodes + (size_t)j * f.nr + i;
+  const float2* row1 = row0 + f.nr;
+  const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
+  const R br0 = (R)n00.x + a * ((R)n01.x - (R)n00.x);
+  const R br1 = (R)n10.x + a * ((R)n11.x - (R)n10.x);
+  const R bz0 = (R)n00.y + a * ((R)n01.y - (R)n00.y);
+  const R bz1 = (R)n10.y + a * ((R)n11.y - (R)n10.y);
+  const R br = br0 + b * (br1 - br0);
+  bz = bz0 + b * (bz1 - bz0);
+  if (r > (R)1e-9) {
+    const R s = br / r;
+    bx = s * x;
+    by = s * y;
+  } else {
+    bx = (R)0;
+    by = (R)0;
+  }
+}
+
+// Propagation state. For FP32 the position and the direction carry Kahan
+// compensation terms (the sums of 1 mm increments into ~800 mm positions and of
+// ~3e-3 increments into unit directions would otherwise drift).
+template <typename R>
+struct State {
+  R x, y, z, tx, ty, tz, lam;
+  R cx, cy, cz;
+  R ctx, cty, ctz;
+};
+
+template <typename R>
+__device__ __forceinline__ void kahan_add(R& s, R& c, R d) {
+  const R y = d - c;
+  const R t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+template <typename R>
+__device__ __forceinline__ void turn(R& t, R& c, R d) {
+  if constexpr (sizeof(R) == 4) {
+    kahan_add(t, c, d);
+  } else {
+    t += d;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void advance(State<R>& st, R dx, R dy, R dz) {
+  if constexpr (sizeof(R) == 4) {
+    kahan_add(st.x, st.cx, dx);
+    kahan_add(st.y, st.cy, dy);
+    kahan_add(st.z, st.cz, dz);
+  } else {
+    st.x += dx;
+    st.y += dy;
+    st.z += dz;
+  }
+}
+
+// One RKN4 step (Nystrom formula for x'' = lam x' x B(x), three field evaluations:
+// start, middle, end). FIELD 0: uniform B_z; FIELD 1: (r, z) map.
+template <typename R, int FIELD>
+__device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, R h) {
+  const R h2 = (R)0.5 * h, hh6 = h * h / (R)6, h6 = h / (R)6;
+  if constexpr (FIELD == 0) {
+    const R a = st.lam * (R)f.bz;
+    const R k1x = a * st.ty, k1y = -a * st.tx;
+    const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y;
+    const R k2x = a * t2y, k2y = -a * t2x;
+    const R t3x = st.tx + h2 * k2x, t3y = st.ty + h2 * k2y;
+    const R k3x = a * t3y, k3y = -a * t3x;
+    const R t4x = st.tx + h * k3x, t4y = st.ty + h * k3y;
+    const R k4x = a * t4y, k4y = -a * t4x;
+    const R dx = h * st.tx + hh6 * (k1x + k2x + k3x);
+    const R dy = h * st.ty + hh6 * (k1y + k2y + k3y);
+    const R dz = h * st.tz;
+    turn(st.tx, st.ctx, h6 * (k1x + (R)2 * (k2x + k3x) + k4x));
+    turn(st.ty, st.cty, h6 * (k1y + (R)2 * (k2y + k3y) + k4y));
+    advance(st, dx, dy, dz);
+  } else {
+    const R l = st.lam;
+    R bx, by, bz;
+    field_rz(f, st.x, st.y, st.z, bx, by, bz);
+    const R k1x = l * (st.ty * bz - st.tz * by);
+    const R k1y = l * (st.tz * bx - st.tx * bz);
+    const R k1z = l * (st.tx * by - st.ty * bx);
+    const R hh8 = h * h * (R)0.125;
+    field_rz(f, st.x + h2 * st.tx + hh8 * k1x, st.y + h2 * st.ty + hh8 * k1y,
+             st.z + h2 * st.tz + hh8 * k1z, bx, by, bz);
+    const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y, t2z = st.tz + h2 * k1z;
+    const R k2x = l * (t2y * bz - t2z * by);
+    const R k2y = l * (t2z * bx - t2x * bz);
+    const R k2z = l * (t2x * by - t2y * bx);
+    const R t3x = st.tx + h2 * k2x, t3y = st.ty + h2 * k2y, t3z = st.tz + h2 * k2z;
+    const R k3x = l * (t3y * bz - t3z * by);
+    const R k3y = l * (t3z * bx - t3x * bz);
+    const R k3z = l * (t3x * by - t3y * bx);
+    const R hh2 = h * h * (R)0.5;
+    field_rz(f, st.x + h * st.tx + hh2 * k3x, st.y + h * st.ty + hh2 * k3y,
+             st.z + h * st.tz + hh2 * k3z, bx, by, bz);
+    const R t4x = st.tx + h * k3x, t4y = st.ty + h * k3y, t4z = st.tz + h * k3z;
+    const R k4x = l * (t4y * bz - t4z * by);
+    const R k4y = l * (t4z * bx - t4x * bz);
+    const R k4z = l * (t4x * by - t4y * bx);
+    const R dx = h * st.tx + hh6 * (k1x + k2x + k3x);
+    const R dy = h * st.ty + hh6 * (k1y + k2y + k3y);
+    const R dz = h * st.tz + hh6 * (k1z + k2z + k3z);
+    turn(st.tx, st.ctx, h6 * (k1x + (R)2 * (k2x + k3x) + k4x));
+    turn(st.ty, st.cty, h6 * (k1y + (R)2 * (k2y + k3y) + k4y));
+    turn(st.tz, st.ctz, h6 * (k1z + (R)2 * (k2z + k3z) + k4z));
+    advance(st, dx, dy, dz);
+  }
+}
+
+// Exact squared distance between the chord p0 + s d (s in [0,1]) and the wire
+// m + t u (|t| <= L, |u| = 1): clamp the chord parameter of the line-line optimum,
+// take the wire's closest parameter for it, and if that leaves [-L, L] clamp it and
+// re-optimise the chord parameter (convexity makes this the global minimum).
+template <typename R>
+__device__ __forceinline__ R seg_wire_d2(R p0x, R p0y, R p0z, R p1x, R p1y, R p1z, R mx, R my,
+                                         R mz, R ux, R uy, R uz, R L) {
+  const R dx = p1x - p0x, dy = p1y - p0y, dz = p1z - p0z;
+  const R rx = p0x - mx, ry = p0y - my, rz = p0z - mz;
+  const R a = dx * dx + dy * dy + dz * dz;
+  const R b = dx * ux + dy * uy + dz * uz;
+  const R e = dx * rx + dy * ry + dz * rz;
+  const R f = ux * rx + uy * ry + uz * rz;
+  const R den = a - b * b;
+  R s = den > (R)1e-6 * a ? (b * f - e) / den : (R)0;
+  s = clampv(s, (R)0, (R)1);
+  const R t = b * s + f;
+  const R tc = clampv(t, -L, L);
+  if (tc != t) s = a > (R)0 ? clampv((tc * b - e) / a, (R)0, (R)1) : (R)0;
+  const R vx = rx + s * dx - tc * ux;
+  const R vy = ry + s * dy - tc * uy;
+  const R vz = rz + s * dz - tc * uz;
+  return vx * vx + vy * vy + vz * vz;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+}  // namespace rkn

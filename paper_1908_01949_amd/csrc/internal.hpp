@@ -1,0 +1,122 @@
+// Internal host-side declarations of librknscan (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rknscan.h"
+#include "device_math.hpp"
+
+namespace rkn {
+
+// Grow-only device buffer owned by the context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p, n > 0 ? n : 16);
+    if (e == hipSuccess) bytes = n > 0 ? n : 16;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+// A tile is up to kTile consecutive seeds of one window (never straddles events).
+constexpr int kTile = 256;
+struct Tile {
+  int32_t window;
+  int32_t event;
+  int32_t n;
+  int32_t pad;
+  int64_t start;   // local flat index of the first seed in the window
+  int64_t gbase;   // global seed index of the first seed
+};
+
+struct ArgminPart {
+  double e;
+  int64_t idx;
+};
+
+// Device copy of a window: FP64 centres/half-widths and counts.
+struct WindowDev {
+  double center[5], half_width[5];
+  int32_t count[5];
+  int32_t event;
+};
+
+}  // namespace rkn
+
+struct rkn_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  int n_cu = 0;
+
+  // geometry
+  int n_wires = 0, n_layers = 0;
+  rkn::DevBuf wire32, wire64;        // HitRec-like rows [n_wires] (drift slot unused)
+  rkn::DevBuf wire_layer;            // int32 [n_wires]
+  rkn::DevBuf wire_wx, wire_wy;      // FP64 mid-point x, y [n_wires] (Hough votes)
+  rkn::DevBuf layer_r;               // float2 (rmin, rmax) [n_layers]
+  std::vector<double> h_layer_rmin, h_layer_rmax;
+  std::vector<int32_t> h_layer_of;
+  std::vector<double> h_wx, h_wy;    // waist (x, y) for host-side checks
+
+  // field
+  int field_kind = -1;               // 0 uniform, 1 rz
+  double bz = 0.0;
+  int nr = 0, nz = 0;
+  double r0 = 0, r1 = 0, z0 = 0, z1 = 0;
+  rkn::DevBuf field_nodes;           // float2 (B_r, B_z) [nz][nr]
+
+  // hits (prepared: sorted by layer within each event)
+  int n_events = 0;
+  int64_t total_hits = 0;
+  int max_hits_event = 0;
+  std::vector<int32_t> h_ev_off;
+  rkn::DevBuf ev_off, hits32, hits64, layer_off, ev_maxdrift;
+  rkn::DevBuf hits_wire;             // int32 wire id per hit, upload order
+  rkn::DevBuf hough_acc, hough_max, hough_cand_n, hough_cand, hough_slots, hough_nsel;
+
+  // per-call work buffers
+  rkn::DevBuf windows, tiles, ev_tiles, parts, counter, mscratch, out_score, out_nin, out_best_i,
+      out_best_e, trace_buf, seeds_buf, perm_buf;
+  std::vector<rkn::DevBuf> extra;
+
+  bool set_err(const std::string& s) {
+    err = s;
+    return false;
+  }
+};
+
+namespace rkn {
+
+rkn::FieldDev field_dev(const rkn_ctx* c);
+
+// Launchers (scan.hip). Return a HIP error code; arguments already validated.
+hipError_t launch_prep_hits(rkn_ctx* c, const int32_t* d_wire_id, const float* d_drift);
+hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
+                       const WindowDev* d_windows, const double* d_seeds5, const int64_t* d_perm,
+                       double* d_score, int32_t* d_nin, int64_t* d_best_i, double* d_best_e,
+                       const int32_t* d_ev_tiles);
+hipError_t launch_trace(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds, const double* d_seeds,
+                        int32_t n_sel, const int32_t* d_steps, double* d_states);
+
+}  // namespace rkn

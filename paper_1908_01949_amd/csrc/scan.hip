@@ -1,0 +1,570 @@
+// The seed-scan kernels for gfx950 (Yeo et al., CTD/WIT 2019, section 2.2, Eq. 1).
+//
+// Work decomposition (one MI355X):
+//   * one lane per seed; a 256-lane workgroup takes tiles of up to 256 seeds of one
+//     event from an atomic queue (persistent grid sized to the resident capacity);
+//   * the event's hits are staged in LDS, ordered by layer, with a 1 mm radial
+//     table that maps a radius range to the range of hits whose layer band (widened
+//     by the largest drift + sqrt(lambda) + 1 mm) it can meet;
+//   * each lane runs B RKN steps in registers and writes the B+1 points to an LDS
+//     column; the wave then walks the union of its lanes' hit ranges with the hit
+//     in scalar registers, tests each (lane, hit) with a sphere bound (all B chords
+//     lie within B h / 2 of the block's middle point) and appends the survivors to
+//     an LDS work list (ballot + mbcnt compaction);
+//   * the list is processed densely: every lane takes one (seed, hit) item, computes
+//     the exact chord/wire distance of the B chords and folds the minimum into the
+//     seed's running minimum (a per-workgroup slab [hit][lane] in HBM, updated with
+//     an integer atomic min on the non-negative float bit pattern: order-free and
+//     deterministic);
+//   * after the last block each lane forms E = sum min((D - d)^2, lambda) in FP64.
+// Both culls are exact: a pair they drop can only have a distance above
+// d + sqrt(lambda), where the term is lambda whatever the distance is.
+#include "internal.hpp"
+
+namespace rkn {
+
+constexpr int kCap = 256;          // work-list entries per wave
+constexpr int kTabBins = 1024;     // 1 mm radial bins, the last one open-ended
+constexpr float kBandMargin = 1.0f;
+
+struct ScanArgs {
+  FieldDev field;
+  const HitRec<float>* hits32;
+  const HitRec<double>* hits64;
+  const int32_t* ev_off;
+  const int32_t* layer_off;   // [n_events][n_layers+1]
+  const float2* layer_r;      // (rmin, rmax) per layer
+  const float* ev_maxdrift;
+  int n_layers;
+  int hits_bytes;             // LDS bytes reserved for hit records
+  const Tile* tiles;
+  int64_t n_tiles;
+  const WindowDev* windows;
+  const double* seeds5;       // explicit seeds [n][5] in scan order (NULL: windows)
+  const int64_t* perm;        // scan order -> caller index (explicit seeds)
+  int* tile_counter;
+  void* mscratch;
+  int64_t slab_stride;        // elements per workgroup slab
+  double R0, charge, h, lambda;
+  int n_steps;
+  double* score;
+  int32_t* nin;
+  ArgminPart* parts;
+};
+
+// ---------------------------------------------------------------------------------
+// Upload-time preparation: per event, order the hits by layer (stable), build the
+// FP32/FP64 hit records and the per-layer offsets, and the event's largest drift.
+__global__ void __launch_bounds__(256)
+prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__ wire_id,
+                 const float* __restrict__ drift, const HitRec<float>* __restrict__ wire32,
+                 const HitRec<double>* __restrict__ wire64, const int32_t* __restrict__ wire_layer,
+                 int n_layers, HitRec<float>* __restrict__ out32, HitRec<double>* __restrict__ out64,
+                 int32_t* __restrict__ layer_off, float* __restrict__ ev_maxdrift) {
+  __shared__ int s_layer[RKN_MAX_HITS_PER_EVENT];
+  __shared__ int s_count[RKN_MAX_LAYERS + 1];
+  __shared__ unsigned int s_max;
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int base = ev_off[e], n = ev_off[e + 1] - base;
+  for (int l = tid; l <= n_layers; l += blockDim.x) s_count[l] = 0;
+  if (tid == 0) s_max = 0u;
+  __syncthreads();
+  unsigned int mymax = 0u;
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int l = wire_layer[wire_id[base + i]];
+    s_layer[i] = l;
+    atomicAdd(&s_count[l], 1);
+    const unsigned int bits = __float_as_uint(drift[base + i]);
+    mymax = bits > mymax ? bits : mymax;
+  }
+  atomicMax(&s_max, mymax);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int l = 0; l < n_layers; ++l) {
+      const int c = s_count[l];
+      s_count[l] = acc;
+      acc += c;
+    }
+    s_count[n_layers] = acc;
+    for (int l = 0; l <= n_layers; ++l) layer_off[(size_t)e * (n_layers + 1) + l] = s_count[l];
+    ev_maxdrift[e] = __uint_as_float(s_max);
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int l = s_layer[i];
+    int rank = s_count[l];
+    for (int j = 0; j < i; ++j) rank += (s_layer[j] == l);
+    const int w = wire_id[base + i];
+    HitRec<float> r32 = wire32[w];
+    HitRec<double> r64 = wire64[w];
+    r32.drift = drift[base + i];
+    r64.drift = (double)drift[base + i];
+    out32[base + rank] = r32;
+    out64[base + rank] = r64;
+  }
+}
+
+hipError_t launch_prep_hits(rkn_ctx* c, const int32_t* d_wire_id, const float* d_drift) {
+  if (c->n_events == 0) return hipSuccess;
+  hipLaunchKernelGGL(prep_hits_kernel, dim3(c->n_events), dim3(256), 0, c->stream,
+                     c->ev_off.as<int32_t>(), d_wire_id, d_drift, c->wire32.as<HitRec<float>>(),
+                     c->wire64.as<HitRec<double>>(), c->wire_layer.as<int32_t>(), c->n_layers,
+                     c->hits32.as<HitRec<float>>(), c->hits64.as<HitRec<double>>(),
+                     c->layer_off.as<int32_t>(), c->ev_maxdrift.as<float>());
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
+
+template <typename R>
+__device__ __forceinline__ const HitRec<R>* hits_of(const ScanArgs& a);
+template <>
+__device__ __forceinline__ const HitRec<float>* hits_of<float>(const ScanArgs& a) { return a.hits32; }
+template <>
+__device__ __forceinline__ const HitRec<double>* hits_of<double>(const ScanArgs& a) { return a.hits64; }
+
+template <typename R>
+__device__ __forceinline__ void atomic_min_nonneg(R* p, R v) {
+  if constexpr (sizeof(R) == 4) {
+    atomicMin(reinterpret_cast<unsigned int*>(p), __float_as_uint(v));
+  } else {
+    atomicMin(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R load_coherent(const R* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Dense pass over a wave's work list: item = (lane << 16) | hit.
+template <typename R, int B>
+__device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, const R* pts,
+                                            const HitRec<R>* s_hits, R* slab, int wave, int lane,
+                                            int nb) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int i = lane; i < n_items; i += 64) {
+    const uint32_t it = items[i];
+    const int s = (int)(it >> 16), hh = (int)(it & 0xffffu);
+    const HitRec<R> w = s_hits[hh];
+    R px = pts[0 * 64 + s], py = pts[1 * 64 + s], pz = pts[2 * 64 + s];
+    R dmin = (R)INFINITY;
+#pragma unroll
+    for (int j = 1; j <= B; ++j) {
+      if (j <= nb) {
+        const R qx = pts[(j * 3 + 0) * 64 + s], qy = pts[(j * 3 + 1) * 64 + s],
+                qz = pts[(j * 3 + 2) * 64 + s];
+        const R d2 = seg_wire_d2<R>(px, py, pz, qx, qy, qz, w.mx, w.my, w.mz, w.ux, w.uy, w.uz, w.L);
+        dmin = d2 < dmin ? d2 : dmin;
+        px = qx;
+        py = qy;
+        pz = qz;
+      }
+    }
+    atomic_min_nonneg(slab + (size_t)hh * kTile + wave * 64 + s, dmin);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R, int FIELD, int B>
+__global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  HitRec<R>* s_hits = reinterpret_cast<HitRec<R>*>(smem);
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(smem + a.hits_bytes);
+  R* s_pts = reinterpret_cast<R*>(smem + a.hits_bytes + kTabBins * 4);
+  uint32_t* s_items = reinterpret_cast<uint32_t*>(s_pts + 4 * (B + 1) * 3 * 64);
+  __shared__ int s_tile;
+  __shared__ double s_red_e[4];
+  __shared__ long long s_red_i[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  R* pts = s_pts + wave * (B + 1) * 3 * 64;
+  uint32_t* items = s_items + wave * kCap;
+  R* slab = reinterpret_cast<R*>(a.mscratch) + (size_t)blockIdx.x * a.slab_stride;
+  const R h = (R)a.h;
+  const double lam = a.lambda;
+  int cur_event = -1;
+
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(a.tile_counter, 1);
+    __syncthreads();
+    const int64_t ti = __builtin_amdgcn_readfirstlane(s_tile);
+    if (ti >= a.n_tiles) break;
+    const Tile t = a.tiles[ti];
+    const int ev = t.event;
+    const int hbase = a.ev_off[ev];
+    const int nh = a.ev_off[ev + 1] - hbase;
+    const HitRec<R>* ghits = hits_of<R>(a) + hbase;
+
+    if (ev != cur_event) {
+      for (int i = tid; i < nh; i += 256) s_hits[i] = ghits[i];
+      const float D = a.ev_maxdrift[ev] + (float)sqrt(lam) + kBandMargin;
+      const int32_t* loff = a.layer_off + (size_t)ev * (a.n_layers + 1);
+      for (int b = tid; b < kTabBins; b += 256) {
+        const float lo_r = (float)b, hi_r = b == kTabBins - 1 ? INFINITY : (float)(b + 1);
+        int l0 = 0;
+        while (l0 < a.n_layers && a.layer_r[l0].y + D < lo_r) ++l0;
+        int l1 = a.n_layers - 1;
+        while (l1 >= 0 && a.layer_r[l1].x - D > hi_r) --l1;
+        uint32_t lo = 0, hi = 0;
+        if (l0 <= l1) {
+          lo = (uint32_t)loff[l0];
+          hi = (uint32_t)loff[l1 + 1];
+        }
+        s_tab[b] = lo | (hi << 16);
+      }
+      cur_event = ev;
+    }
+
+    // ---- seed of this lane ------------------------------------------------------
+    const bool in_tile = tid < t.n;
+    bool valid = in_tile;
+    int64_t gidx = t.gbase + tid;
+    State<R> st;
+    {
+      double v[5];
+      if (a.seeds5) {
+        const int64_t pos = t.start + (in_tile ? tid : 0);
+#pragma unroll
+        for (int d = 0; d < 5; ++d) v[d] = a.seeds5[pos * 5 + d];
+        gidx = a.perm[pos];
+      } else {
+        const WindowDev& W = a.windows[t.window];
+        int64_t k = t.start + (in_tile ? tid : 0);
+        int64_t kd[5];
+#pragma unroll
+        for (int d = 4; d >= 0; --d) {
+          const int64_t n = W.count[d];
+          kd[d] = k % n;
+          k /= n;
+        }
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+          v[d] = W.count[d] <= 1 ? W.center[d]
+                                 : W.center[d] - W.half_width[d] +
+                                       2.0 * W.half_width[d] * (double)kd[d] / (double)(W.count[d] - 1);
+        }
+      }
+      const double pm = sqrt(v[2] * v[2] + v[3] * v[3] + v[4] * v[4]);
+      valid = valid && (pm >= 1e-3);
+      const double ipm = valid ? 1.0 / pm : 0.0;
+      st.x = (R)(a.R0 * cos(v[0]));
+      st.y = (R)(a.R0 * sin(v[0]));
+      st.z = (R)v[1];
+      st.tx = valid ? (R)(v[2] * ipm) : (R)1;
+      st.ty = valid ? (R)(v[3] * ipm) : (R)0;
+      st.tz = valid ? (R)(v[4] * ipm) : (R)0;
+      st.lam = valid ? (R)(kKappa * a.charge * ipm) : (R)0;
+      st.cx = st.cy = st.cz = (R)0;
+      st.ctx = st.cty = st.ctz = (R)0;
+    }
+    for (int i = 0; i < nh; ++i) slab[(size_t)i * kTile + tid] = (R)INFINITY;
+    __threadfence_block();
+    __syncthreads();
+
+    const int nblocks = (a.n_steps + B - 1) / B;
+    const R Kcull = (R)(0.5 * B * a.h + sqrt(lam) + (double)kBandMargin);
+    for (int blk = 0; blk < nblocks; ++blk) {
+      const int nb = min(B, a.n_steps - blk * B);
+      const int jc = nb / 2;
+      pts[0 * 64 + lane] = st.x;
+      pts[1 * 64 + lane] = st.y;
+      pts[2 * 64 + lane] = st.z;
+      R r2min = st.x * st.x + st.y * st.y, r2max = r2min;
+      R cx = st.x, cy = st.y, cz = st.z;
+#pragma unroll
+      for (int j = 1; j <= B; ++j) {
+        if (j <= nb) rkn_step<R, FIELD>(st, a.field, h);
+        pts[(j * 3 + 0) * 64 + lane] = st.x;
+        pts[(j * 3 + 1) * 64 + lane] = st.y;
+        pts[(j * 3 + 2) * 64 + lane] = st.z;
+        const R r2 = st.x * st.x + st.y * st.y;
+        r2min = r2 < r2min ? r2 : r2min;
+        r2max = r2 > r2max ? r2 : r2max;
+        if (j == jc) {
+          cx = st.x;
+          cy = st.y;
+          cz = st.z;
+        }
+      }
+      // radial range of the block's chords (a chord point is within h/2 of an endpoint)
+      const float rmin = fmaxf((float)sqrt(r2min) - 0.5f * (float)a.h, 0.0f);
+      const float rmax = (float)sqrt(r2max);
+      // clamp in float first: fminf/fmaxf map NaN to the bound, so the index is in range
+      const int b_lo = (int)fminf(fmaxf(rmin, 0.0f), (float)(kTabBins - 1));
+      const int b_hi = (int)fminf(fmaxf(rmax, 0.0f), (float)(kTabBins - 1));
+      const int hlo = valid ? (int)(s_tab[b_lo] & 0xffffu) : 0x7fffffff;
+      const int hhi = valid ? (int)(s_tab[b_hi] >> 16) : 0;
+      const int H_lo = wave_min_i32(hlo), H_hi = wave_max_i32(hhi);
+      int n_items = 0;
+      for (int hh = H_lo; hh < H_hi; ++hh) {
+        const HitRec<R> w = load_hit_uniform(ghits, hh);
+        const R rx = cx - w.mx, ry = cy - w.my, rz = cz - w.mz;
+        const R tt = rx * w.ux + ry * w.uy + rz * w.uz;
+        const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
+        const R thr = Kcull + w.drift;
+        const bool pass = valid && (d2 <= thr * thr);
+        const uint64_t m = __ballot(pass);
+        if (m) {
+          if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
+          n_items += (int)__popcll(m);
+          if (n_items > kCap - 64) {
+            flush_items<R, B>(items, n_items, pts, s_hits, slab, wave, lane, nb);
+            n_items = 0;
+          }
+        }
+      }
+      if (n_items) flush_items<R, B>(items, n_items, pts, s_hits, slab, wave, lane, nb);
+    }
+    __threadfence();
+
+    // ---- score (Eq. 1), in FP64 ---------------------------------------------------
+    double E = 0.0;
+    int cnt = 0;
+    if (valid) {
+      for (int i = 0; i < nh; ++i) {
+        const R m2 = load_coherent(slab + (size_t)i * kTile + tid);
+        const double r = sqrt((double)m2) - (double)s_hits[i].drift;
+        const double tq = r * r;
+        if (tq < lam) {
+          E += tq;
+          ++cnt;
+        } else {
+          E += lam;
+        }
+      }
+    } else {
+      E = INFINITY;
+    }
+    long long idx = in_tile ? (long long)gidx : (long long)0x7fffffffffffffffLL;
+    if (in_tile) {
+      if (a.score) a.score[gidx] = E;
+      if (a.nin) a.nin[gidx] = cnt;
+    }
+    // ---- argmin of the tile (E, then index) -------------------------------------
+    double be = in_tile ? E : INFINITY;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double oe = __shfl_xor(be, o, 64);
+      const long long oi = __shfl_xor(idx, o, 64);
+      if (oe < be || (oe == be && oi < idx)) {
+        be = oe;
+        idx = oi;
+      }
+    }
+    if (lane == 0) {
+      s_red_e[wave] = be;
+      s_red_i[wave] = idx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int k = 1; k < 4; ++k)
+        if (s_red_e[k] < be || (s_red_e[k] == be && s_red_i[k] < idx)) {
+          be = s_red_e[k];
+          idx = s_red_i[k];
+        }
+      a.parts[ti].e = be;
+      a.parts[ti].idx = idx;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256)
+event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restrict__ ev_tiles,
+                    int64_t* best_i, double* best_e) {
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int t0 = ev_tiles[e], t1 = ev_tiles[e + 1];
+  double be = INFINITY;
+  long long bi = 0x7fffffffffffffffLL;
+  for (int t = t0 + tid; t < t1; t += 256) {
+    const ArgminPart p = parts[t];
+    if (p.e < be || (p.e == be && p.idx < bi)) {
+      be = p.e;
+      bi = p.idx;
+    }
+  }
+  __shared__ double se[256];
+  __shared__ long long si[256];
+  se[tid] = be;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double oe = se[tid + s];
+      const long long oi = si[tid + s];
+      if (oe < se[tid] || (oe == se[tid] && oi < si[tid])) {
+        se[tid] = oe;
+        si[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const bool none = t1 <= t0;
+    best_i[e] = none ? -1 : si[0];
+    best_e[e] = none ? INFINITY : se[0];
+  }
+}
+
+template <typename R, int FIELD, int B>
+static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t n_tiles) {
+  const int hits_bytes = ((c->max_hits_event * (int)sizeof(HitRec<R>)) + 255) & ~255;
+  a.hits_bytes = hits_bytes;
+  const size_t smem = (size_t)hits_bytes + kTabBins * 4 + 4 * (B + 1) * 3 * 64 * sizeof(R) +
+                      4 * kCap * sizeof(uint32_t);
+  if (smem > 65536) return hipErrorInvalidConfiguration;
+  auto kern = scan_kernel<R, FIELD, B>;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, smem);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  int64_t grid = (int64_t)per_cu * c->n_cu;
+  if (grid > n_tiles) grid = n_tiles;
+  if (grid < 1) grid = 1;
+  a.slab_stride = (int64_t)(c->max_hits_event > 0 ? c->max_hits_event : 1) * kTile;
+  e = c->mscratch.ensure((size_t)grid * a.slab_stride * sizeof(R));
+  if (e != hipSuccess) return e;
+  a.mscratch = c->mscratch.p;
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, c->stream, a.tile_counter);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), smem, c->stream, a);
+  return hipGetLastError();
+}
+
+FieldDev field_dev(const rkn_ctx* c) {
+  FieldDev f{};
+  f.bz = c->bz;
+  if (c->field_kind == 1) {
+    f.nodes = c->field_nodes.as<float2>();
+    f.nr = c->nr;
+    f.nz = c->nz;
+    f.r0 = c->r0;
+    f.z0 = c->z0;
+    f.inv_dr = (double)(c->nr - 1) / (c->r1 - c->r0);
+    f.inv_dz = (double)(c->nz - 1) / (c->z1 - c->z0);
+  }
+  return f;
+}
+
+hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
+                       const WindowDev* d_windows, const double* d_seeds5, const int64_t* d_perm,
+                       double* d_score, int32_t* d_nin, int64_t* d_best_i, double* d_best_e,
+                       const int32_t* d_ev_tiles) {
+  hipError_t e = c->parts.ensure(sizeof(ArgminPart) * (size_t)(n_tiles > 0 ? n_tiles : 1));
+  if (e != hipSuccess) return e;
+  e = c->counter.ensure(64);
+  if (e != hipSuccess) return e;
+  ScanArgs a{};
+  a.field = field_dev(c);
+  a.hits32 = c->hits32.as<HitRec<float>>();
+  a.hits64 = c->hits64.as<HitRec<double>>();
+  a.ev_off = c->ev_off.as<int32_t>();
+  a.layer_off = c->layer_off.as<int32_t>();
+  a.layer_r = c->layer_r.as<float2>();
+  a.ev_maxdrift = c->ev_maxdrift.as<float>();
+  a.n_layers = c->n_layers;
+  a.tiles = d_tiles;
+  a.n_tiles = n_tiles;
+  a.windows = d_windows;
+  a.seeds5 = d_seeds5;
+  a.perm = d_perm;
+  a.tile_counter = c->counter.as<int>();
+  a.R0 = p->R0;
+  a.charge = p->charge;
+  a.h = p->step_mm;
+  a.lambda = p->lambda_mm2;
+  a.n_steps = p->n_steps;
+  a.score = d_score;
+  a.nin = d_nin;
+  a.parts = c->parts.as<ArgminPart>();
+  if (n_tiles > 0) {
+    const int B = p->block_steps;
+    if (p->precision == 64) {
+      e = c->field_kind == 0 ? launch_scan_t<double, 0, 4>(c, a, n_tiles)
+                             : launch_scan_t<double, 1, 4>(c, a, n_tiles);
+    } else if (c->field_kind == 0) {
+      e = B == 4 ? launch_scan_t<float, 0, 4>(c, a, n_tiles) : launch_scan_t<float, 0, 8>(c, a, n_tiles);
+    } else {
+      e = B == 4 ? launch_scan_t<float, 1, 4>(c, a, n_tiles) : launch_scan_t<float, 1, 8>(c, a, n_tiles);
+    }
+    if (e != hipSuccess) return e;
+  }
+  if (c->n_events > 0) {
+    hipLaunchKernelGGL(event_argmin_kernel, dim3(c->n_events), dim3(256), 0, c->stream,
+                       c->parts.as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+template <typename R, int FIELD>
+__global__ void __launch_bounds__(256)
+trace_kernel(FieldDev f, double R0, double charge, double hstep, int64_t n_seeds,
+             const double* __restrict__ seeds, int n_sel, const int32_t* __restrict__ steps,
+             double* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_seeds) return;
+  const double* v = seeds + 5 * s;
+  const double pm = sqrt(v[2] * v[2] + v[3] * v[3] + v[4] * v[4]);
+  double* o = out + (size_t)s * n_sel * 6;
+  if (!(pm >= 1e-3)) {
+    for (int k = 0; k < 6 * n_sel; ++k) o[k] = NAN;
+    return;
+  }
+  State<R> st;
+  st.x = (R)(R0 * cos(v[0]));
+  st.y = (R)(R0 * sin(v[0]));
+  st.z = (R)v[1];
+  st.tx = (R)(v[2] / pm);
+  st.ty = (R)(v[3] / pm);
+  st.tz = (R)(v[4] / pm);
+  st.lam = (R)(kKappa * charge / pm);
+  st.cx = st.cy = st.cz = (R)0;
+      st.ctx = st.cty = st.ctz = (R)0;
+  const R h = (R)hstep;
+  int n = 0;
+  for (int k = 0; k < n_sel; ++k) {
+    const int target = steps[k];
+    while (n < target) {
+      rkn_step<R, FIELD>(st, f, h);
+      ++n;
+    }
+    o[6 * k + 0] = (double)st.x;
+    o[6 * k + 1] = (double)st.y;
+    o[6 * k + 2] = (double)st.z;
+    o[6 * k + 3] = (double)st.tx;
+    o[6 * k + 4] = (double)st.ty;
+    o[6 * k + 5] = (double)st.tz;
+  }
+}
+
+hipError_t launch_trace(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds, const double* d_seeds,
+                        int32_t n_sel, const int32_t* d_steps, double* d_states) {
+  const FieldDev f = field_dev(c);
+  const dim3 grid((unsigned)((n_seeds + 255) / 256)), block(256);
+  if (n_seeds == 0) return hipSuccess;
+  if (p->precision == 64) {
+    if (c->field_kind == 0)
+      hipLaunchKernelGGL((trace_kernel<double, 0>), grid, block, 0, c->stream, f, p->R0, p->charge,
+                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+    else
+      hipLaunchKernelGGL((trace_kernel<double, 1>), grid, block, 0, c->stream, f, p->R0, p->charge,
+                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+  } else {
+    if (c->field_kind == 0)
+      hipLaunchKernelGGL((trace_kernel<float, 0>), grid, block, 0, c->stream, f, p->R0, p->charge,
+                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+    else
+      hipLaunchKernelGGL((trace_kernel<float, 1>), grid, block, 0, c->stream, f, p->R0, p->charge,
+                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rkn

@@ -1,0 +1,292 @@
+"""Python binding of librknscan (ctypes): argument marshalling only.
+
+Every function here has the name of the C entry point it calls (include/rknscan.h)
+and does no arithmetic of the scan; all work runs in the HIP kernels of
+``lib/librknscan.so``. Arrays are numpy (host) or torch tensors (device: their
+``data_ptr()`` is passed with ``RKN_PTR_DEVICE``). Importing this module on a
+machine without the built library raises immediately: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "librknscan.so")
+
+RKN_OK = 0
+RKN_E_ARG = -1
+RKN_E_STATE = -2
+RKN_E_NOMEM = -3
+RKN_E_DEVICE = -4
+RKN_E_CAPACITY = -5
+RKN_E_UNSUPPORTED = -6
+RKN_PTR_DEVICE = 1
+RKN_MAX_HITS_PER_EVENT = 512
+RKN_MAX_LAYERS = 64
+
+STATUS_NAMES = {0: "RKN_OK", -1: "RKN_E_ARG", -2: "RKN_E_STATE", -3: "RKN_E_NOMEM",
+                -4: "RKN_E_DEVICE", -5: "RKN_E_CAPACITY", -6: "RKN_E_UNSUPPORTED"}
+
+
+class RknError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rkn_window(C.Structure):
+    _fields_ = [("event", C.c_int32), ("candidate", C.c_int32), ("center", C.c_double * 5),
+                ("half_width", C.c_double * 5), ("count", C.c_int32 * 5), ("pad", C.c_int32)]
+
+
+class rkn_hough_params(C.Structure):
+    _fields_ = [("n_xy", C.c_int32), ("n_r", C.c_int32), ("xy_half", C.c_double),
+                ("r_min", C.c_double), ("r_max", C.c_double), ("min_votes", C.c_int32),
+                ("max_cand", C.c_int32), ("R0", C.c_double), ("charge", C.c_double),
+                ("b_ref", C.c_double), ("gran", C.c_double * 5), ("center_z", C.c_double),
+                ("center_pz", C.c_double), ("count", C.c_int32 * 5), ("grow", C.c_int32 * 5),
+                ("count_max", C.c_int32), ("pad", C.c_int32), ("max_seeds_window", C.c_int64)]
+
+
+class rkn_scan_params(C.Structure):
+    _fields_ = [("R0", C.c_double), ("charge", C.c_double), ("step_mm", C.c_double),
+                ("lambda_mm2", C.c_double), ("n_steps", C.c_int32), ("precision", C.c_int32),
+                ("ptr_flags", C.c_int32), ("block_steps", C.c_int32)]
+
+
+# Exported symbols and their ctypes signatures (the C header declares the same set).
+_P = C.c_void_p
+_SIGS = {
+    "rkn_version": (C.c_char_p, []),
+    "rkn_create": (C.c_int32, [C.c_int32, _P, C.POINTER(_P)]),
+    "rkn_destroy": (None, [_P]),
+    "rkn_last_error": (C.c_char_p, [_P]),
+    "rkn_synchronize": (C.c_int32, [_P]),
+    "rkn_upload_geometry": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int32, _P, _P]),
+    "rkn_upload_field_uniform": (C.c_int32, [_P, C.c_double]),
+    "rkn_upload_field_rz": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, _P, _P]),
+    "rkn_upload_hits": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "rkn_hough_seed_windows": (C.c_int32, [_P, _P, C.c_int32, _P, _P]),
+    "rkn_hough_accumulator": (C.c_int32, [_P, _P, C.c_int32, C.c_int32, _P]),
+    "rkn_scan_windows": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
+    "rkn_scan_seeds": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "rkn_trace": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P]),
+}
+
+_lib = None
+
+
+def preload_hip_runtime() -> None:
+    """Load the system HIP runtime by its bare name, process-wide, before torch.
+
+    torch's HIP library asks for ``libamdhip64.so`` while this library asks for
+    ``libamdhip64.so.7``; loading the runtime first under the bare name makes both
+    bind to one copy. If torch is already imported, this library binds to torch's
+    runtime through the shared soname instead. Either way one runtime serves both.
+    """
+    if "torch" not in sys.modules:
+        C.CDLL("libamdhip64.so", mode=C.RTLD_GLOBAL)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librknscan.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        preload_hip_runtime()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with paper_1908_01949_amd/build.py "
+                              "(the seed scan has no CPU fallback)")
+        lib = C.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return list(_SIGS)
+
+
+def _ptr(a):
+    """Pointer of a numpy array or torch tensor (None passes NULL)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _host(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _check(ctx, status):
+    if status != RKN_OK:
+        msg = load_library().rkn_last_error(ctx)
+        raise RknError(status, msg.decode() if msg else "")
+
+
+def rkn_version() -> str:
+    return load_library().rkn_version().decode()
+
+
+def rkn_create(device: int = 0, stream: int | None = None):
+    out = _P()
+    st = load_library().rkn_create(device, stream, C.byref(out))
+    if st != RKN_OK:
+        raise RknError(st, "rkn_create failed")
+    return out
+
+
+def rkn_destroy(ctx) -> None:
+    load_library().rkn_destroy(ctx)
+
+
+def rkn_last_error(ctx) -> str:
+    return load_library().rkn_last_error(ctx).decode()
+
+
+def rkn_synchronize(ctx) -> None:
+    _check(ctx, load_library().rkn_synchronize(ctx))
+
+
+def rkn_upload_geometry(ctx, mx, my, mz, ux, uy, uz, half_len, layer_of, layer_rmin, layer_rmax) -> None:
+    a = [_host(v, np.float64) for v in (mx, my, mz, ux, uy, uz, half_len)]
+    lo = _host(layer_of, np.int32)
+    r0 = _host(layer_rmin, np.float64); r1 = _host(layer_rmax, np.float64)
+    _check(ctx, load_library().rkn_upload_geometry(ctx, a[0].size, *[_ptr(v) for v in a], _ptr(lo),
+                                                   r0.size, _ptr(r0), _ptr(r1)))
+
+
+def rkn_upload_field_uniform(ctx, bz: float) -> None:
+    _check(ctx, load_library().rkn_upload_field_uniform(ctx, float(bz)))
+
+
+def rkn_upload_field_rz(ctx, r0, r1, z0, z1, br, bz) -> None:
+    br = _host(br, np.float32); bz = _host(bz, np.float32)
+    nz, nr = br.shape
+    _check(ctx, load_library().rkn_upload_field_rz(ctx, nr, nz, float(r0), float(r1), float(z0), float(z1),
+                                                   _ptr(br), _ptr(bz)))
+
+
+def rkn_upload_hits(ctx, ev_off, wire_id, drift) -> None:
+    off = _host(ev_off, np.int32); w = _host(wire_id, np.int32); d = _host(drift, np.float32)
+    _check(ctx, load_library().rkn_upload_hits(ctx, off.size - 1, _ptr(off), _ptr(w), _ptr(d)))
+
+
+def make_scan_params(R0=500.0, charge=-1.0, step_mm=1.0, lambda_mm2=64.0, n_steps=2000, precision=32,
+                     ptr_flags=0, block_steps=0) -> rkn_scan_params:
+    return rkn_scan_params(R0, charge, step_mm, lambda_mm2, n_steps, precision, ptr_flags, block_steps)
+
+
+def make_hough_params(**kw) -> rkn_hough_params:
+    d = dict(n_xy=256, n_r=64, xy_half=512.0, r_min=160.0, r_max=416.0, min_votes=6, max_cand=4,
+             R0=500.0, charge=-1.0, b_ref=1.0, gran=(0.01, 50.0, 2.5, 2.5, 5.0), center_z=0.0,
+             center_pz=0.0, count=(12, 12, 12, 12, 12), grow=(0, 0, 0, 0, 0), count_max=12,
+             max_seeds_window=100000)
+    d.update(kw)
+    hp = rkn_hough_params()
+    for k, v in d.items():
+        if k in ("gran", "count", "grow"):
+            arr = getattr(hp, k)
+            for i in range(5):
+                arr[i] = v[i]
+        else:
+            setattr(hp, k, v)
+    return hp
+
+
+def windows_to_c(windows) -> C.Array:
+    """numpy structured windows (synth.WINDOW_DTYPE) -> rkn_window array."""
+    arr = (rkn_window * max(len(windows), 1))()
+    C.memmove(arr, np.ascontiguousarray(windows).ctypes.data, len(windows) * C.sizeof(rkn_window))
+    return arr
+
+
+def windows_from_c(arr, n):
+    from paper_1908_01949_amd.synth import WINDOW_DTYPE
+    out = np.zeros(n, WINDOW_DTYPE)
+    C.memmove(out.ctypes.data, arr, n * C.sizeof(rkn_window))
+    return out
+
+
+def rkn_hough_seed_windows(ctx, hp: rkn_hough_params, max_windows: int = 4096):
+    arr = (rkn_window * max(max_windows, 1))()
+    n = C.c_int32()
+    _check(ctx, load_library().rkn_hough_seed_windows(ctx, C.byref(hp), max_windows, arr, C.byref(n)))
+    return windows_from_c(arr, n.value)
+
+
+def rkn_hough_accumulator(ctx, hp: rkn_hough_params, event: int, out=None):
+    if out is None:
+        out = np.zeros(hp.n_xy * hp.n_xy * hp.n_r, np.uint32)
+    flags = RKN_PTR_DEVICE if hasattr(out, "data_ptr") else 0
+    _check(ctx, load_library().rkn_hough_accumulator(ctx, C.byref(hp), event, flags, _ptr(out)))
+    return out
+
+
+def rkn_scan_windows(ctx, p: rkn_scan_params, windows, score=None, n_in=None, best_index=None,
+                     best_score=None):
+    """Outputs: numpy arrays (host) or torch tensors (set p.ptr_flags = RKN_PTR_DEVICE)."""
+    w = windows_to_c(windows)
+    _check(ctx, load_library().rkn_scan_windows(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
+                                                _ptr(best_index), _ptr(best_score)))
+    return score, n_in, best_index, best_score
+
+
+def rkn_scan_seeds(ctx, p: rkn_scan_params, seed_event, seeds5, score=None, n_in=None, best_index=None,
+                   best_score=None):
+    se = _host(seed_event, np.int32)
+    s5 = np.asarray(seeds5, np.float64).reshape(-1, 5)
+    cols = [np.ascontiguousarray(s5[:, d]) for d in range(5)]
+    _check(ctx, load_library().rkn_scan_seeds(ctx, C.byref(p), se.size, _ptr(se), *[_ptr(c) for c in cols],
+                                              _ptr(score), _ptr(n_in), _ptr(best_index), _ptr(best_score)))
+    return score, n_in, best_index, best_score
+
+
+def rkn_trace(ctx, p: rkn_scan_params, seeds5, step_idx, states=None):
+    s5 = np.ascontiguousarray(np.asarray(seeds5, np.float64).reshape(-1, 5))
+    st = _host(step_idx, np.int32)
+    if states is None:
+        states = np.zeros((s5.shape[0], st.size, 6))
+    _check(ctx, load_library().rkn_trace(ctx, C.byref(p), s5.shape[0], _ptr(s5), st.size, _ptr(st),
+                                         _ptr(states)))
+    return states
+
+
+class Context:
+    """Convenience owner of an rkn_ctx (destroyed with the object)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.ctx = rkn_create(device, stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            rkn_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload_geometry(self, geo):
+        rkn_upload_geometry(self.ctx, geo.mx, geo.my, geo.mz, geo.ux, geo.uy, geo.uz, geo.half_len,
+                            geo.layer_of, geo.layer_rmin, geo.layer_rmax)
+
+    def upload_field(self, field):
+        if field.kind == "uniform":
+            rkn_upload_field_uniform(self.ctx, field.bz)
+        else:
+            rkn_upload_field_rz(self.ctx, field.r0, field.r1, field.z0, field.z1, field.br_grid, field.bz_grid)
+
+    def upload_hits(self, ev_off, wire_id, drift):
+        rkn_upload_hits(self.ctx, ev_off, wire_id, drift)

@@ -9,6 +9,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def _preload_runtime():
+    # One HIP runtime per process: load the system runtime by its bare name before
+    # anything imports torch (see paper_1908_01949_amd.rknscan.preload_hip_runtime).
+    try:
+        from paper_1908_01949_amd import rknscan
+        rknscan.preload_hip_runtime()
+    except OSError:
+        pass
+
+
+_preload_runtime()
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")

@@ -1,0 +1,52 @@
+"""The C-ABI library builds, loads and exports every symbol its header declares (CPU only)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rknscan.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rkn_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_header_symbols():
+    from paper_1908_01949_amd import rknscan
+    if not os.path.exists(rknscan.LIB_PATH):
+        pytest.fail("librknscan.so is not built (run __graft_entry__.build())")
+    out = subprocess.run(["nm", "-D", "--defined-only", rknscan.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    decl = declared_symbols()
+    assert decl, "no declarations parsed"
+    missing = [s for s in decl if s not in exported]
+    assert not missing, missing
+    # the binding wraps exactly the declared entry points
+    assert sorted(rknscan.exported_symbols()) == decl
+    lib = rknscan.load_library()
+    for s in decl:
+        assert getattr(lib, s) is not None
+    assert "gfx950" in rknscan.rkn_version()
+
+
+def test_struct_layouts_match_header():
+    import ctypes
+    from paper_1908_01949_amd import rknscan, synth
+    assert ctypes.sizeof(rknscan.rkn_window) == 112 == synth.WINDOW_DTYPE.itemsize
+    assert ctypes.sizeof(rknscan.rkn_scan_params) == 48
+    assert ctypes.sizeof(rknscan.rkn_hough_params) == 4 * 2 + 8 * 3 + 4 * 2 + 8 * 3 + 8 * 5 + 8 * 2 + 4 * 5 * 2 + 4 * 2 + 8
+
+
+def test_no_oracle_import_in_product():
+    """The product path (package and binding) never references the oracle."""
+    pkg = os.path.join(ROOT, "paper_1908_01949_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "rkn_oracle" not in txt and "liboracle" not in txt, f

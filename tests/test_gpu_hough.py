@@ -1,0 +1,75 @@
+"""GPU parity of the circle Hough stage (section 2.1): bit-exact accumulator, identical
+peaks and window counts, window centres within 1e-12 of the oracle's."""
+import numpy as np
+import pytest
+
+from paper_1908_01949_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rk():
+    from paper_1908_01949_amd import rknscan
+    rknscan.load_library()
+    return rknscan
+
+
+@pytest.fixture(scope="module")
+def events(geo, ufield):
+    evs = [synth.event_fixed_total(geo, ufield, s, n_total=150, noise_frac=0.2) for s in range(3)]
+    evs.append(synth.event_multi_turn(geo, ufield, 2))
+    evs.append(synth.Event(np.array([7], np.int32), np.array([1.0], np.float32), np.zeros(1, bool),
+                           np.zeros(1, np.int32), np.zeros(1), np.zeros((0, 5)), np.zeros(0)))
+    return evs
+
+
+def test_accumulator_bit_exact(rk, geo, ufield, orc_u, events):
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(ufield)
+    off, wid, dr = synth.pack_events(events)
+    c.upload_hits(off, wid, dr)
+    hp = rk.make_hough_params()
+    ohp = orc_u.hough_params()
+    for e in range(len(events)):
+        print(f"hough accumulator event {e}", flush=True)
+        g = rk.rkn_hough_accumulator(c.ctx, hp, e)
+        o = orc_u.hough_accumulate(ohp, wid[off[e]:off[e + 1]])
+        assert np.array_equal(g, o)
+    c.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(count=(4, 3, 4, 4, 3), grow=(1, 0, 1, 1, 0), count_max=10,
+                                             max_seeds_window=2000, max_cand=3, min_votes=8)])
+def test_windows_match_oracle(rk, geo, ufield, orc_u, events, kw):
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(ufield)
+    off, wid, dr = synth.pack_events(events)
+    c.upload_hits(off, wid, dr)
+    base = dict(gran=(0.1 / 11, 1000.0 / 11, 10.0 / 11, 10.0 / 11, 120.0 / 11), max_seeds_window=10 ** 9)
+    base.update(kw)
+    g = rk.rkn_hough_seed_windows(c.ctx, rk.make_hough_params(**base))
+    o = orc_u.hough_seed_windows(orc_u.hough_params(**base), off, wid)
+    print(f"windows gpu {len(g)} oracle {len(o)}", flush=True)
+    assert len(g) == len(o) >= 4
+    assert np.array_equal(g["event"], o["event"]) and np.array_equal(g["candidate"], o["candidate"])
+    assert np.array_equal(g["count"], o["count"])
+    np.testing.assert_allclose(g["center"], o["center"], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(g["half_width"], o["half_width"], rtol=1e-15, atol=0)
+    # capacity: too small an output reports the required count
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_hough_seed_windows(c.ctx, rk.make_hough_params(**base), max_windows=1)
+    assert e.value.status == rk.RKN_E_CAPACITY
+    c.close()
+
+
+def test_hough_param_errors(rk, geo, ufield, events):
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(ufield)
+    off, wid, dr = synth.pack_events(events)
+    c.upload_hits(off, wid, dr)
+    for bad in (dict(xy_half=512.001), dict(n_r=65), dict(max_cand=0), dict(r_max=100.0)):
+        with pytest.raises(rk.RknError) as e:
+            rk.rkn_hough_seed_windows(c.ctx, rk.make_hough_params(**bad))
+        assert e.value.status == rk.RKN_E_ARG
+    c.close()

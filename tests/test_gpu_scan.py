@@ -1,0 +1,264 @@
+"""GPU parity of the propagation and the scan against the FP64 oracle (through the C ABI).
+
+Tolerances (stated, not tuned): FP64 trajectories <= 1e-9 mm, FP32 trajectories
+<= 0.05 mm after three turns, scores <= 1e-4 relative, best-seed index identical
+except at a near-tie (runner-up within 2e-4 relative), n_in identical except for a
+hit on the lambda boundary.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1908_01949_amd import synth
+from tests import parity_util as pu
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rk():
+    from paper_1908_01949_amd import rknscan
+    rknscan.load_library()
+    return rknscan
+
+
+@pytest.fixture(scope="module")
+def ctx_u(rk, geo, ufield):
+    c = rk.Context(0)
+    c.upload_geometry(geo)
+    c.upload_field(ufield)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_s(rk, geo, sfield):
+    c = rk.Context(0)
+    c.upload_geometry(geo)
+    c.upload_field(sfield)
+    yield c
+    c.close()
+
+
+def _seeds(rng, n, pz_max=20.0):
+    th = rng.uniform(-np.pi, np.pi, n)
+    p = rng.uniform(70, 106, n)
+    pz = rng.uniform(-pz_max, pz_max, n)
+    pt = np.sqrt(p * p - pz * pz)
+    ph = th + np.pi / 2 + rng.uniform(-0.6, 0.6, n)
+    return np.stack([th, rng.uniform(-300, 300, n), pt * np.cos(ph), pt * np.sin(ph), pz], -1)
+
+
+# ---------------------------------------------------------------------------------------
+# trajectories (rkn_trace)
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("fieldname,prec,tol", [("u", 64, 1e-9), ("u", 32, 0.05),
+                                                ("s", 64, 1e-9), ("s", 32, 0.05)])
+def test_trace_parity(rk, ctx_u, ctx_s, orc_u, orc_s, fieldname, prec, tol):
+    ctx, O = (ctx_u, orc_u) if fieldname == "u" else (ctx_s, orc_s)
+    _note(f"trace parity field={fieldname} precision={prec}")
+    rng = np.random.default_rng(100 + prec)
+    seeds = _seeds(rng, 64)
+    steps = np.array([0, 1, 7, 500, 2200, 4400, 6600], np.int32)   # 3 turns = 6600 mm
+    p = rk.make_scan_params(n_steps=6600, precision=prec)
+    g = rk.rkn_trace(ctx.ctx, p, seeds, steps)
+    o = O.trace(O.params(n_steps=6600), seeds, steps)
+    dpos = np.linalg.norm(g[..., :3] - o[..., :3], axis=-1)
+    _note(f"  max position error {dpos.max():.3e} mm (tol {tol})")
+    assert dpos.max() <= tol
+    assert np.abs(g[..., 3:] - o[..., 3:]).max() <= (1e-12 if prec == 64 else 1e-5)
+
+
+# ---------------------------------------------------------------------------------------
+# scans
+# ---------------------------------------------------------------------------------------
+def _scan_both(rk, ctx, O, ev_list, windows, n_steps, prec, lam=64.0, block_steps=0, mode=1):
+    off, wid, dr = synth.pack_events(ev_list)
+    ctx.upload_hits(off, wid, dr)
+    total = int(sum(int(np.prod(w["count"].astype(np.int64))) for w in windows))
+    p = rk.make_scan_params(n_steps=n_steps, precision=prec, lambda_mm2=lam, block_steps=block_steps)
+    score = np.zeros(total); nin = np.zeros(total, np.int32)
+    bi = np.zeros(len(ev_list), np.int64); bs = np.zeros(len(ev_list))
+    rk.rkn_scan_windows(ctx.ctx, p, windows, score, nin, bi, bs)
+    osc, onin, obi, obs, _ = O.scan_windows(O.params(n_steps=n_steps, lambda_mm2=lam), off, wid, dr,
+                                            windows, mode=mode)
+    return score, nin, bi, bs, osc, onin, obi, obs
+
+
+def test_scan_single_turn_fp64(rk, ctx_u, orc_u, ev1):
+    """One event, uniform 1 T, FP64, 6^5 = 7776 seeds over theta+-0.3, z+-100, p+-10, 2000 steps."""
+    _note("scan single-turn FP64 6^5")
+    w = synth.make_windows([(0, 0, ev1.truth_seeds[0], [0.3, 100, 10, 10, 10], [6] * 5)])
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_u, orc_u, [ev1], w, 2000, 64)
+    rel = pu.check_scores(score, osc, rel=1e-9, abs_=1e-9)
+    _note(f"  max rel score error {rel:.2e}")
+    assert np.array_equal(nin, onin)
+    pu.check_best(bi[0], osc)
+    assert bs[0] == pytest.approx(osc.min(), rel=1e-9)
+
+
+def test_scan_multi_turn_fp32(rk, ctx_u, orc_u, geo, ufield):
+    """2-3 turn event with 30 % noise, FP32 propagation, 6000 steps, 4^5 grid + ragged tail."""
+    _note("scan multi-turn FP32 4^5+ragged")
+    ev = synth.event_multi_turn(geo, ufield, 0)
+    t = ev.truth_seeds[0]
+    w = synth.make_windows([(0, 0, t, [0.04, 15, 2, 2, 2], [4, 4, 4, 4, 4]),
+                            (0, 1, t + np.array([0.01, 5, 0.5, -0.5, 0.3]), [0.01, 3, 0.5, 0.5, 0.5], [3, 1, 5, 1, 7])])
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_u, orc_u, [ev], w, 6000, 32)
+    rel = pu.check_scores(score, osc)
+    _note(f"  max rel score error {rel:.2e}")
+    pu.check_nin(nin, onin)
+    pu.check_best(bi[0], osc)
+
+
+def test_scan_solenoid_fp32(rk, ctx_s, orc_s, geo, sfield):
+    """Field map (65x129 bilinear) event with 150 hits, 20 % noise, FP32."""
+    _note("scan solenoid FP32 3^5")
+    ev = synth.event_fixed_total(geo, sfield, 0, n_total=150, noise_frac=0.2)
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], [0.03, 20, 3, 3, 3], [3] * 5)])
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_s, orc_s, [ev], w, 6000, 32)
+    rel = pu.check_scores(score, osc)
+    _note(f"  max rel score error {rel:.2e}")
+    pu.check_nin(nin, onin)
+    pu.check_best(bi[0], osc)
+
+
+@pytest.mark.parametrize("block_steps", [4, 8])
+def test_scan_block_steps_and_ragged_steps(rk, ctx_u, orc_u, ev1, block_steps):
+    """n_steps not a multiple of the block; every block size gives the oracle's scores."""
+    _note(f"scan block_steps={block_steps} n_steps=1999")
+    w = synth.make_windows([(0, 0, ev1.truth_seeds[0], [0.1, 30, 4, 4, 4], [3, 3, 3, 3, 3])])
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_u, orc_u, [ev1], w, 1999, 32,
+                                                         block_steps=block_steps)
+    pu.check_scores(score, osc)
+    pu.check_best(bi[0], osc)
+
+
+def test_scan_multi_event_edge_cases(rk, ctx_u, orc_u, geo, ufield, ev1):
+    """Several events: one with no hits, one with no window, a seed with |p| ~ 0, lambda = 16."""
+    _note("scan multi-event edge cases")
+    ev2 = synth.event_single_turn(geo, ufield, 5)
+    empty = synth.Event(np.zeros(0, np.int32), np.zeros(0, np.float32), np.zeros(0, bool),
+                        np.zeros(0, np.int32), np.zeros(0), np.zeros((0, 5)), np.zeros(0))
+    evs = [ev1, empty, ev2, ev1]
+    w = synth.make_windows([
+        (0, 0, ev1.truth_seeds[0], [0.05, 10, 2, 2, 2], [2, 2, 3, 2, 2]),
+        (1, 0, ev1.truth_seeds[0], [0.05, 10, 2, 2, 2], [2, 1, 1, 1, 3]),
+        (2, 0, ev2.truth_seeds[0], [0.05, 10, 2, 2, 2], [3, 3, 3, 3, 3]),
+        (2, 1, [0.0, 0.0, 0.0, 0.0, 0.0], [0, 0, 0, 0, 0], [1, 1, 1, 1, 1]),     # |p| = 0
+    ])
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_u, orc_u, evs, w, 2000, 32, lam=16.0)
+    pu.check_scores(score, osc)
+    assert np.all(score[48:51] == 0.0)                 # no hits: E = 0
+    assert np.isinf(score[-1]) and nin[-1] == 0
+    assert bi[3] == -1 and np.isinf(bs[3])             # event with no window
+    assert bi[1] == 48                                  # all-zero plateau: lowest index
+    for e in (0, 2):
+        assert bi[e] == obi[e] or pu.check_best(bi[e], osc)
+
+
+def test_scan_seeds_matches_oracle(rk, ctx_u, orc_u, geo, ufield, ev1):
+    """Explicit seed list in scrambled event order across two events."""
+    _note("scan explicit seeds")
+    ev2 = synth.event_single_turn(geo, ufield, 6)
+    off, wid, dr = synth.pack_events([ev1, ev2])
+    ctx_u.upload_hits(off, wid, dr)
+    rng = np.random.default_rng(4)
+    s1 = synth.random_seeds(rng, ev1.truth_seeds[0], [0.05, 20, 3, 3, 3], 300)
+    s2 = synth.random_seeds(rng, ev2.truth_seeds[0], [0.05, 20, 3, 3, 3], 200)
+    seeds = np.concatenate([s1, s2]); sev = np.r_[np.zeros(300), np.ones(200)].astype(np.int32)
+    perm = rng.permutation(500)
+    seeds, sev = seeds[perm], sev[perm]
+    p = rk.make_scan_params(n_steps=2000, precision=32)
+    score = np.zeros(500); nin = np.zeros(500, np.int32); bi = np.zeros(2, np.int64); bs = np.zeros(2)
+    rk.rkn_scan_seeds(ctx_u.ctx, p, sev, seeds, score, nin, bi, bs)
+    osc, onin, obi, obs = orc_u.scan_seeds(orc_u.params(n_steps=2000), off, wid, dr, sev, seeds)
+    pu.check_scores(score, osc)
+    pu.check_nin(nin, onin)
+    for e in range(2):
+        idx = np.nonzero(sev == e)[0]
+        g = int(bi[e]); assert sev[g] == e
+        best = idx[np.argmin(osc[idx])]
+        assert g == best or osc[g] <= osc[best] * (1 + pu.NEAR_TIE)
+
+
+def test_scan_device_outputs_torch(rk, geo, ufield, orc_u, ev1):
+    """Device-pointer outputs on torch's current stream (stream-ordered)."""
+    import torch
+    _note("scan device outputs")
+    stream = torch.cuda.current_stream().cuda_stream
+    c = rk.Context(0, stream)
+    c.upload_geometry(geo); c.upload_field(ufield)
+    off, wid, dr = synth.pack_events([ev1])
+    c.upload_hits(off, wid, dr)
+    w = synth.make_windows([(0, 0, ev1.truth_seeds[0], [0.1, 30, 4, 4, 4], [3] * 5)])
+    p = rk.make_scan_params(n_steps=2000, precision=32, ptr_flags=rk.RKN_PTR_DEVICE)
+    score = torch.zeros(243, dtype=torch.float64, device="cuda")
+    nin = torch.zeros(243, dtype=torch.int32, device="cuda")
+    bi = torch.zeros(1, dtype=torch.int64, device="cuda"); bs = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rk.rkn_scan_windows(c.ctx, p, w, score, nin, bi, bs)
+    torch.cuda.synchronize()
+    osc, onin, obi, obs, _ = orc_u.scan_windows(orc_u.params(n_steps=2000), off, wid, dr, w)
+    pu.check_scores(score.cpu().numpy(), osc)
+    pu.check_best(int(bi.cpu()[0]), osc)
+    c.close()
+
+
+def test_scan_repeatable(rk, ctx_u, ev1):
+    """Two identical scans give bit-identical scores (no order-dependent reductions)."""
+    off, wid, dr = synth.pack_events([ev1])
+    ctx_u.upload_hits(off, wid, dr)
+    w = synth.make_windows([(0, 0, ev1.truth_seeds[0], [0.3, 100, 10, 10, 10], [4] * 5)])
+    p = rk.make_scan_params(n_steps=2000, precision=32)
+    outs = []
+    for _ in range(2):
+        s = np.zeros(1024); n = np.zeros(1024, np.int32); bi = np.zeros(1, np.int64); bs = np.zeros(1)
+        rk.rkn_scan_windows(ctx_u.ctx, p, w, s, n, bi, bs)
+        outs.append((s, n, bi))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2][0] == outs[1][2][0]
+
+
+def test_argument_errors(rk, geo, ufield, ev1):
+    """Invalid arguments and call order give error codes, never a crash."""
+    c = rk.Context(0)
+    w = synth.make_windows([(0, 0, ev1.truth_seeds[0], [0.1, 30, 4, 4, 4], [2] * 5)])
+    p = rk.make_scan_params()
+    out = (np.zeros(32), np.zeros(32, np.int32), np.zeros(1, np.int64), np.zeros(1))
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_scan_windows(c.ctx, p, w, *out)
+    assert e.value.status == rk.RKN_E_STATE
+    c.upload_geometry(geo)
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_upload_hits(c.ctx, [0, 2], [0, 99999], [1.0, 1.0])
+    assert e.value.status == rk.RKN_E_ARG
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_upload_hits(c.ctx, [0, 1], [3], [float("nan")])
+    assert e.value.status == rk.RKN_E_ARG
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_upload_hits(c.ctx, [0, 600], np.arange(600), np.ones(600))
+    assert e.value.status == rk.RKN_E_CAPACITY
+    c.upload_field(ufield)
+    off, wid, dr = synth.pack_events([ev1])
+    c.upload_hits(off, wid, dr)
+    for bad in (dict(n_steps=0), dict(step_mm=-1.0), dict(precision=16), dict(lambda_mm2=float("nan")),
+                dict(block_steps=3)):
+        with pytest.raises(rk.RknError) as e:
+            rk.rkn_scan_windows(c.ctx, rk.make_scan_params(**bad), w, *out)
+        assert e.value.status == rk.RKN_E_ARG
+    wbad = w.copy(); wbad[0]["count"][2] = 0
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_scan_windows(c.ctx, p, wbad, *out)
+    assert e.value.status == rk.RKN_E_ARG
+    wbad = w.copy(); wbad[0]["event"] = 3
+    with pytest.raises(rk.RknError):
+        rk.rkn_scan_windows(c.ctx, p, wbad, *out)
+    # the context still works after errors
+    rk.rkn_scan_windows(c.ctx, p, w, *out)
+    assert np.isfinite(out[0]).all()
+    c.close()

@@ -82,7 +82,7 @@ def test_window_from_circle_geometry(orc_u):
     """Window centre = outward crossing of the bin-centre circle with r = R0 (independent solve)."""
     a, b, k = 150, 90, 50
     hp = orc_u.hough_params(count=(5, 4, 5, 5, 3), grow=(1, 0, 1, 1, 0), count_max=9,
-                            max_seeds_event=10 ** 9, center_z=12.0, center_pz=-3.0, b_ref=1.0)
+                            max_seeds_window=10 ** 9, center_z=12.0, center_pz=-3.0, b_ref=1.0)
     acc = np.zeros(256 * 256 * 64, np.uint32)
     flat = (a * 256 + b) * 64 + k
     acc[flat] = 20
@@ -117,7 +117,7 @@ def test_window_from_circle_geometry(orc_u):
     assert ow.half_width[0] == pytest.approx(0.01 * 2.5)
     # cap: the largest count is reduced first (lowest dimension on ties)
     hp2 = orc_u.hough_params(count=(5, 4, 5, 5, 3), grow=(1, 0, 1, 1, 0), count_max=9,
-                             max_seeds_event=6 * 4 * 6 * 6 * 3 - 1)
+                             max_seeds_window=6 * 4 * 6 * 6 * 3 - 1)
     ow2 = oracle.OrcWindow()
     oracle.lib().orc_hough_window(ctypes.byref(hp2), acc.ctypes.data, flat, ctypes.byref(ow2))
     assert list(ow2.count) == [5, 4, 6, 6, 3]
@@ -126,7 +126,7 @@ def test_window_from_circle_geometry(orc_u):
 def test_hough_windows_cover_truth(geo, ufield, orc_u):
     """On a single-turn event the best window contains the truth transverse seed (sanity)."""
     ev = synth.event_fixed_total(geo, ufield, 0, n_total=150, noise_frac=0.2)
-    hp = orc_u.hough_params(count=(12, 12, 12, 12, 12), count_max=12, max_seeds_event=10 ** 9,
+    hp = orc_u.hough_params(count=(12, 12, 12, 12, 12), count_max=12, max_seeds_window=10 ** 9,
                             gran=(0.1 / 11, 1000.0 / 11, 10.0 / 11, 10.0 / 11, 120.0 / 11))
     off = np.array([0, ev.wire_id.size], np.int32)
     ws = orc_u.hough_seed_windows(hp, off, ev.wire_id)
