@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched RKN seed scan on one MI355X.
+
+One step = one pass of the hot path over a batch of 512 synthetic events: circle
+Hough stage and seed windows for every event, one persistent scan launch over all
+seeds (6000 RKN steps of 1 mm, FP32 propagation, FP64 scores) and the per-event
+argmin, replayed from captured HIP graphs with inputs already in HBM.
+
+Prints one JSON line (stdout). Progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from paper_1908_01949_amd import rknscan as rk  # noqa: E402  (loads the HIP runtime first)
+from paper_1908_01949_amd import flops, synth  # noqa: E402
+
+METRIC = "RKN seed-steps/s & events/s, %FP32 vector peak; plain scan vs adjoint-refined"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cfg4_hough_params(field):
+    """Window rule of the batched workload: 1e3-1e5 seeds per event."""
+    return rk.make_hough_params(
+        b_ref=field.b_ref, min_votes=6, max_cand=4,
+        gran=(0.01, 100.0, 2.5, 2.5, 12.0), center_z=0.0, center_pz=0.0,
+        count=(4, 6, 4, 4, 6), grow=(1, 0, 1, 1, 0), count_max=10, max_seeds_window=25000)
+
+
+def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_steps, lam, seconds):
+    """The FP64 oracle timed on this host's cores on a bounded random sample of the
+    same batch; also counts the pruned algorithm's work for the roofline."""
+    import oracle
+    O = oracle.Oracle(geo, field)
+    prm = O.params(n_steps=n_steps, lambda_mm2=lam)
+    off, wid, dr = synth.pack_events(events)
+    sizes = np.array([int(np.prod(w["count"].astype(np.int64))) for w in windows])
+    wbase = np.concatenate([[0], np.cumsum(sizes)])
+    total = int(wbase[-1])
+    rng = np.random.default_rng(2024)
+
+    def draw(n):
+        g = np.sort(rng.choice(total, size=n, replace=False))
+        k = np.searchsorted(wbase, g, side="right") - 1
+        seeds = np.array([O.window_seed(windows[kk], gg - wbase[kk]) for kk, gg in zip(k, g)])
+        return g, windows["event"][k].astype(np.int32), seeds
+
+    cores = os.cpu_count() or 1
+    g, se, seeds = draw(min(64, total))
+    t = time.perf_counter()
+    sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1)
+    dt = time.perf_counter() - t
+    n = int(min(total, max(64, 64 * seconds / max(dt, 1e-3))))
+    if n > 64:
+        g, se, seeds = draw(n)
+        t = time.perf_counter()
+        sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1)
+        dt = time.perf_counter() - t
+    rel = float(np.max(np.abs(gpu_scores[g] - sc) / np.maximum(np.abs(sc), 1e-12)))
+    # pruned-algorithm work counts on a sub-sample
+    cull = pairs = 0
+    m = min(64, len(g))
+    for i in range(m):
+        e = int(se[i])
+        _, _, cu, pk = O.score_blocked(prm, seeds[i], wid[off[e]:off[e + 1]], dr[off[e]:off[e + 1]], 8)
+        cull += cu; pairs += pk
+    ss = m * n_steps
+    return dict(value=len(g) * n_steps / dt, unit="seed-steps/s", cores=cores, kind="oracle",
+                sample=f"{len(g)} seeds drawn uniformly from the {total} of the batch, {n_steps} steps each, "
+                       f"FP64 band-pruned oracle, OpenMP over seeds, {dt:.1f} s"), \
+        dict(cull_per_step=cull / ss, pairs_per_step=pairs / ss, sample_max_rel_score_err=rel)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--events", type=int, default=512)
+    ap.add_argument("--rkn-steps", type=int, default=6000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (events shard across GPUs without any "
+              "exchange; see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    log(f"generating {args.events} events ...")
+    t0 = time.time()
+    geo = synth.make_geometry()
+    field = synth.solenoid_field()
+    events = synth.events_batch(geo, field, args.events, seed=0, n_steps=args.rkn_steps)
+    off, wid, dr = synth.pack_events(events)
+    log(f"  {wid.size} hits in {time.time() - t0:.1f} s")
+
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = rk.Context(0, stream)
+    ctx.upload_geometry(geo)
+    ctx.upload_field(field)
+    ctx.upload_hits(off, wid, dr)
+    lam = 64.0
+    sp = rk.make_scan_params(n_steps=args.rkn_steps, precision=32, lambda_mm2=lam)
+    hp = cfg4_hough_params(field)
+    rk.rkn_batch_plan(ctx.ctx, hp, sp)
+    ne = args.events
+    bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+    for i in range(args.warmup):
+        rk.rkn_batch_launch(ctx.ctx, bi, bs)
+        log(f"warmup {i}: {rk.rkn_batch_info(ctx.ctx)}")
+    torch.cuda.synchronize()
+    ms_h, ms_s = [], []
+    t = time.perf_counter()
+    for i in range(args.steps):
+        rk.rkn_batch_launch(ctx.ctx, bi, bs)
+        nw, ns, th, ts = rk.rkn_batch_info(ctx.ctx)
+        ms_h.append(th); ms_s.append(ts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    seed_steps = ns * args.rkn_steps
+    value = seed_steps * args.steps / dt
+    log(f"timed {args.steps} steps: {dt * 1e3 / args.steps:.1f} ms/step, {nw} windows, {ns} seeds, "
+        f"hough {np.mean(ms_h):.2f} ms, scan {np.mean(ms_s):.2f} ms")
+
+    cpu = None
+    work = None
+    if not args.no_cpu_baseline:
+        windows, scores, _, ev_seed_off = rk.rkn_batch_results(ctx.ctx, ne)
+        cpu, work = cpu_baseline_leg(geo, field, events, windows, ev_seed_off, scores, args.rkn_steps,
+                                     lam, args.cpu_seconds)
+        log(f"cpu baseline: {cpu}")
+        log(f"work counts: {work}")
+    roof = None
+    if work is not None:
+        f_alg = flops.per_seed_step("rz", work["cull_per_step"], work["pairs_per_step"])
+        achieved = f_alg * seed_steps / (np.mean(ms_s) * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=flops.PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / flops.PEAK_FP32_TFLOPS, 4), traffic=None,
+                    flops_per_seed_step=round(f_alg, 2), kernel="scan_kernel<float, rz field, B=8>")
+    out = {
+        "metric": METRIC, "value": value, "unit": "seed-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{ne} events, 1-3 e- with p~U[60,105] MeV/c, 40-300 hits with 10-40% noise, "
+                               f"65x129 (r,z) solenoid map, circle-Hough windows (1e3-1e5 seeds/event), "
+                               f"{args.rkn_steps} RKN steps of 1 mm, FP64 scores and argmin",
+                   "n_events": ne, "n_seeds": int(ns), "n_windows": int(nw), "rkn_steps": args.rkn_steps,
+                   "lambda_mm2": lam},
+        "events_per_s": ne * args.steps / dt,
+        "ms_hough": float(np.mean(ms_h)), "ms_scan": float(np.mean(ms_s)),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    if work is not None:
+        out["sample_max_rel_score_err"] = work["sample_max_rel_score_err"]
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -186,6 +186,34 @@ rkn_status rkn_scan_seeds(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seed
 rkn_status rkn_trace(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, const double *seeds5,
                      int32_t n_sel, const int32_t *step_idx, double *states);
 
+/* ---- Batched scan of every uploaded event ---------------------------------------
+ * The Hough stage, the expansion of its windows into seed tiles, one persistent
+ * scan launch over all tiles (an atomic work queue of up to 256 seeds of one
+ * window each) and the per-event argmin, captured once as HIP graphs on the
+ * context's stream. Re-plan after uploading new hits or geometry. */
+
+/* Validate the parameters, size every buffer for the worst case
+ * (n_events x max_cand windows of at most min(max_seeds_window, count_max^5)
+ * seeds) and capture the graphs. sp->ptr_flags chooses host or device outputs of
+ * rkn_batch_launch. */
+rkn_status rkn_batch_plan(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp);
+
+/* Replay the graphs on the current hits; best_index/best_score per event (global
+ * seed index of the batch, -1/+inf for an event without windows) as in
+ * rkn_scan_windows. Either may be NULL. */
+rkn_status rkn_batch_launch(rkn_ctx *ctx, int64_t *best_index, double *best_score);
+
+/* After a launch (waits for it): number of windows and seeds of the batch, and the
+ * HIP-event time of the Hough+expansion graph and of the scan graph, in ms. */
+rkn_status rkn_batch_info(rkn_ctx *ctx, int32_t *n_windows, int64_t *n_seeds, float *ms_hough,
+                          float *ms_scan);
+
+/* After a launch: the windows (host, ordered by event), per-seed scores and n_in
+ * (host, global seed order) and the per-event first seed index ev_seed_off
+ * [n_events+1]. Any output may be NULL; RKN_E_CAPACITY if a capacity is short. */
+rkn_status rkn_batch_results(rkn_ctx *ctx, int32_t max_windows, rkn_window *windows, int32_t *n_windows,
+                             int64_t max_seeds, double *score, int32_t *n_in, int64_t *ev_seed_off);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,8 @@ def lib():
         P = C.c_void_p
         _lib.orc_score.restype = C.c_double
         _lib.orc_score.argtypes = [P, P, P, P, C.c_int32, P, P, C.c_int32, P, P]
+        _lib.orc_score_blocked.restype = C.c_double
+        _lib.orc_score_blocked.argtypes = [P, P, P, P, C.c_int32, P, P, C.c_int32, P, P, P]
         _lib.orc_seg_wire_dist2.restype = C.c_double
         _lib.orc_seg_wire_dist2.argtypes = [P, P, P, P, C.c_double]
         _lib.orc_field_eval.argtypes = [P, P, P]
@@ -162,6 +164,15 @@ class Oracle:
         E = lib().orc_score(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size,
                             _ptr(w), _ptr(d), mode, C.byref(n_in), C.byref(pairs))
         return E, n_in.value, pairs.value
+
+    def score_blocked(self, prm, seed, wire_id, drift, block=8):
+        """E with the kernel's exact block pruning; returns (E, n_in, cull tests, pairs)."""
+        s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
+        d = np.ascontiguousarray(drift, np.float32)
+        n_in = C.c_int32(); cull = C.c_int64(); pairs = C.c_int64()
+        E = lib().orc_score_blocked(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size,
+                                    _ptr(w), _ptr(d), int(block), C.byref(n_in), C.byref(cull), C.byref(pairs))
+        return E, n_in.value, cull.value, pairs.value
 
     @staticmethod
     def window_struct(w) -> OrcWindow:

@@ -79,6 +79,12 @@ double orc_score(const orc_geometry *g, const orc_field *f, const orc_params *p,
                  int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t mode,
                  int32_t *n_in, int64_t *pairs);
 
+/* The same score with the GPU kernel's two-level exact pruning in blocks of B
+ * steps; cull = sphere tests made, pairs = chord/hit distances evaluated. */
+double orc_score_blocked(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+                         int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t B,
+                         int32_t *n_in, int64_t *cull, int64_t *pairs);
+
 /* Seed grid: flat index (theta slowest, pz fastest) -> seed. */
 void orc_window_seed(const orc_window *w, int64_t flat, double seed[5]);
 

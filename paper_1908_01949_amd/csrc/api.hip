@@ -120,6 +120,7 @@ void rkn_destroy(rkn_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  rkn::batch_release(c);
   DevBuf* bufs[] = {&c->wire32, &c->wire64, &c->wire_layer, &c->layer_r, &c->field_nodes, &c->ev_off,
                     &c->hits32, &c->hits64, &c->layer_off, &c->ev_maxdrift, &c->windows, &c->tiles,
                     &c->ev_tiles, &c->parts, &c->counter, &c->mscratch, &c->out_score, &c->out_nin,
@@ -194,6 +195,7 @@ rkn_status rkn_upload_geometry(rkn_ctx* c, int32_t n_wires, const double* mx, co
   c->h_wy.assign(my, my + n_wires);
   c->h_ev_off.clear();       // hits refer to the old wire table
   c->n_events = 0;
+  rkn::batch_release(c);
   return RKN_OK;
 }
 
@@ -260,6 +262,7 @@ rkn_status rkn_upload_hits(rkn_ctx* c, int32_t n_events, const int32_t* ev_off, 
     if (!std::isfinite(drift[i]) || drift[i] < 0) return arg_err(c, "drift must be finite and >= 0 at hit " + std::to_string(i));
   }
   RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
+  rkn::batch_release(c);   // a planned batch refers to the previous events
   DevBuf d_drift;
   DevBuf& d_wid = c->hits_wire;
   hipError_t e = upload(c->ev_off, ev_off, (size_t)n_events + 1, c->stream);

@@ -25,26 +25,7 @@ namespace rkn {
 constexpr int kHoughCells = 256;
 constexpr int kMaxNr = 64;
 constexpr int kCandCap = 4096;
-constexpr int kMaxCand = 64;
 constexpr int kEventChunk = 32;
-
-struct HoughDev {
-  int n_xy, n_r;
-  int half_q, wxy_q, rmin_q, wr_q;   // in 2^-8 mm
-  int min_votes, max_cand;
-  double R0, charge, b_ref, xy_half, r_min, wxy, wr;
-  double gran[5];
-  double center_z, center_pz;
-  int count[5], grow[5];
-  int count_max;
-  long long max_seeds;
-};
-
-struct WinSlot {
-  WindowDev w;
-  int32_t valid;
-  int32_t pad;
-};
 
 __global__ void __launch_bounds__(kHoughCells)
 hough_vote_kernel(HoughDev hp, const int32_t* __restrict__ ev_off, const int32_t* __restrict__ wire_id,
@@ -273,16 +254,14 @@ hough_select_kernel(HoughDev hp, const uint32_t* __restrict__ acc, int ev0,
 
 }  // namespace rkn
 
-using namespace rkn;
+namespace rkn {
 
-namespace {
-
-rkn_status herr(rkn_ctx* c, hipError_t e, const char* where) {
+static rkn_status herr(rkn_ctx* c, hipError_t e, const char* where) {
   c->err = std::string(where) + ": " + hipGetErrorString(e);
   return e == hipErrorOutOfMemory ? RKN_E_NOMEM : RKN_E_DEVICE;
 }
 
-bool dyadic(double v) { return std::isfinite(v) && v * 256.0 == std::floor(v * 256.0) && std::fabs(v) < 1e6; }
+static bool dyadic(double v) { return std::isfinite(v) && v * 256.0 == std::floor(v * 256.0) && std::fabs(v) < 1e6; }
 
 rkn_status make_hough_dev(rkn_ctx* c, const rkn_hough_params* p, HoughDev& h) {
   if (!p) {
@@ -343,11 +322,10 @@ rkn_status make_hough_dev(rkn_ctx* c, const rkn_hough_params* p, HoughDev& h) {
 }
 
 // Accumulate, find peaks and build windows for events [ev0, ev0+n); device slots.
-hipError_t run_hough_chunk(rkn_ctx* c, const HoughDev& h, int ev0, int n, bool windows) {
+static hipError_t run_hough_chunk(rkn_ctx* c, const HoughDev& h, int ev0, int n, bool windows) {
   const size_t nb = (size_t)h.n_xy * h.n_xy * h.n_r;
   hipError_t e;
   DevBuf& acc = c->hough_acc;
-  if ((e = acc.ensure(sizeof(uint32_t) * nb * n)) != hipSuccess) return e;
   hipLaunchKernelGGL(hough_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream,
                      c->hough_max.as<uint32_t>() + ev0, n);
   hipLaunchKernelGGL(hough_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream,
@@ -369,9 +347,12 @@ hipError_t run_hough_chunk(rkn_ctx* c, const HoughDev& h, int ev0, int n, bool w
   return hipGetLastError();
 }
 
-hipError_t ensure_hough_buffers(rkn_ctx* c) {
+hipError_t ensure_hough_buffers(rkn_ctx* c, const HoughDev& h) {
   hipError_t e;
   const int ne = c->n_events;
+  const size_t nb = (size_t)h.n_xy * h.n_xy * h.n_r;
+  if ((e = c->hough_acc.ensure(sizeof(uint32_t) * nb * std::min(kEventChunk, std::max(ne, 1)))) != hipSuccess)
+    return e;
   if ((e = c->hough_max.ensure(sizeof(uint32_t) * ne)) != hipSuccess) return e;
   if ((e = c->hough_cand_n.ensure(sizeof(uint32_t) * ne)) != hipSuccess) return e;
   if ((e = c->hough_cand.ensure(sizeof(uint2) * (size_t)kCandCap * ne)) != hipSuccess) return e;
@@ -380,7 +361,18 @@ hipError_t ensure_hough_buffers(rkn_ctx* c) {
   return hipSuccess;
 }
 
-}  // namespace
+hipError_t queue_hough_all(rkn_ctx* c, const HoughDev& h) {
+  for (int ev0 = 0; ev0 < c->n_events; ev0 += kEventChunk) {
+    const int n = std::min(kEventChunk, c->n_events - ev0);
+    hipError_t e = run_hough_chunk(c, h, ev0, n, true);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace rkn
+
+using namespace rkn;
 
 extern "C" {
 
@@ -400,7 +392,7 @@ rkn_status rkn_hough_accumulator(rkn_ctx* c, const rkn_hough_params* hp, int32_t
   }
   hipError_t e;
   if ((e = hipSetDevice(c->device)) != hipSuccess) return herr(c, e, "hipSetDevice");
-  if ((e = ensure_hough_buffers(c)) != hipSuccess) return herr(c, e, "hough alloc");
+  if ((e = ensure_hough_buffers(c, h)) != hipSuccess) return herr(c, e, "hough alloc");
   if ((e = run_hough_chunk(c, h, event, 1, false)) != hipSuccess) return herr(c, e, "hough vote");
   const size_t nb = (size_t)h.n_xy * h.n_xy * h.n_r;
   e = hipMemcpyAsync(acc, c->hough_acc.p, nb * sizeof(uint32_t),
@@ -426,15 +418,12 @@ rkn_status rkn_hough_seed_windows(rkn_ctx* c, const rkn_hough_params* hp, int32_
   }
   hipError_t e;
   if ((e = hipSetDevice(c->device)) != hipSuccess) return herr(c, e, "hipSetDevice");
-  if ((e = ensure_hough_buffers(c)) != hipSuccess) return herr(c, e, "hough alloc");
+  if ((e = ensure_hough_buffers(c, h)) != hipSuccess) return herr(c, e, "hough alloc");
   const int ne = c->n_events;
   std::vector<WinSlot> slots((size_t)kMaxCand * ne);
   std::vector<int32_t> nsel(ne);
   std::vector<uint32_t> ncand(ne);
-  for (int ev0 = 0; ev0 < ne; ev0 += kEventChunk) {
-    const int n = std::min(kEventChunk, ne - ev0);
-    if ((e = run_hough_chunk(c, h, ev0, n, true)) != hipSuccess) return herr(c, e, "hough");
-  }
+  if ((e = queue_hough_all(c, h)) != hipSuccess) return herr(c, e, "hough");
   e = hipMemcpyAsync(slots.data(), c->hough_slots.p, sizeof(WinSlot) * slots.size(), hipMemcpyDeviceToHost,
                      c->stream);
   if (e == hipSuccess)

@@ -60,6 +60,26 @@ struct WindowDev {
   int32_t event;
 };
 
+constexpr int kMaxCand = 64;     // Hough candidates kept per event, upper bound
+
+struct HoughDev {
+  int n_xy, n_r;
+  int half_q, wxy_q, rmin_q, wr_q;   // in 2^-8 mm
+  int min_votes, max_cand;
+  double R0, charge, b_ref, xy_half, r_min, wxy, wr;
+  double gran[5];
+  double center_z, center_pz;
+  int count[5], grow[5];
+  int count_max;
+  long long max_seeds;
+};
+
+struct WinSlot {
+  WindowDev w;
+  int32_t valid;
+  int32_t pad;
+};
+
 }  // namespace rkn
 
 struct rkn_ctx {
@@ -100,6 +120,17 @@ struct rkn_ctx {
       out_best_e, trace_buf, seeds_buf, perm_buf;
   std::vector<rkn::DevBuf> extra;
 
+  // batched path (planned once, launched as captured graphs)
+  bool batch_ready = false;
+  rkn_scan_params batch_scan{};
+  rkn::HoughDev batch_hough{};
+  int64_t batch_max_tiles = 0, batch_max_seeds = 0;
+  hipGraph_t g_hough = nullptr, g_scan = nullptr;
+  hipGraphExec_t x_hough = nullptr, x_scan = nullptr;
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr;
+  rkn::DevBuf b_windows, b_tiles, b_ev_tiles, b_counts, b_ev_seed, b_score, b_nin, b_best_i, b_best_e,
+      b_ev_scratch;
+
   bool set_err(const std::string& s) {
     err = s;
     return false;
@@ -118,5 +149,19 @@ hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, co
                        const int32_t* d_ev_tiles);
 hipError_t launch_trace(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds, const double* d_seeds,
                         int32_t n_sel, const int32_t* d_steps, double* d_states);
+
+// Hough (hough.hip): validate parameters; queue the whole stage for every event
+// (no host synchronisation, no allocation: capturable once buffers exist).
+rkn_status make_hough_dev(rkn_ctx* c, const rkn_hough_params* p, HoughDev& h);
+hipError_t ensure_hough_buffers(rkn_ctx* c, const HoughDev& h);
+hipError_t queue_hough_all(rkn_ctx* c, const HoughDev& h);
+
+// Release the batched path's graphs, events and buffers (batch.hip).
+void batch_release(rkn_ctx* c);
+
+// Scan launch whose tile count is read from device memory (batched path).
+hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_tiles, const int32_t* d_n_tiles,
+                           const Tile* d_tiles, const WindowDev* d_windows, double* d_score, int32_t* d_nin,
+                           int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only);
 
 }  // namespace rkn

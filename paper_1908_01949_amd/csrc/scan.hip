@@ -39,6 +39,7 @@ struct ScanArgs {
   int hits_bytes;             // LDS bytes reserved for hit records
   const Tile* tiles;
   int64_t n_tiles;
+  const int32_t* n_tiles_dev;   // if set, the tile count is read here (captured launches)
   const WindowDev* windows;
   const double* seeds5;       // explicit seeds [n][5] in scan order (NULL: windows)
   const int64_t* perm;        // scan order -> caller index (explicit seeds)
@@ -184,6 +185,7 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
   __shared__ long long s_red_i[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n_tiles = a.n_tiles_dev ? (int64_t)*a.n_tiles_dev : a.n_tiles;
   R* pts = s_pts + wave * (B + 1) * 3 * 64;
   uint32_t* items = s_items + wave * kCap;
   R* slab = reinterpret_cast<R*>(a.mscratch) + (size_t)blockIdx.x * a.slab_stride;
@@ -195,7 +197,7 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
     if (tid == 0) s_tile = atomicAdd(a.tile_counter, 1);
     __syncthreads();
     const int64_t ti = __builtin_amdgcn_readfirstlane(s_tile);
-    if (ti >= a.n_tiles) break;
+    if (ti >= n_tiles) break;
     const Tile t = a.tiles[ti];
     const int ev = t.event;
     const int hbase = a.ev_off[ev];
@@ -414,7 +416,7 @@ event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restr
 }
 
 template <typename R, int FIELD, int B>
-static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t n_tiles) {
+static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only) {
   const int hits_bytes = ((c->max_hits_event * (int)sizeof(HitRec<R>)) + 255) & ~255;
   a.hits_bytes = hits_bytes;
   const size_t smem = (size_t)hits_bytes + kTabBins * 4 + 4 * (B + 1) * 3 * 64 * sizeof(R) +
@@ -426,15 +428,34 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t n_tiles) {
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   int64_t grid = (int64_t)per_cu * c->n_cu;
-  if (grid > n_tiles) grid = n_tiles;
+  if (grid > max_tiles) grid = max_tiles;
   if (grid < 1) grid = 1;
   a.slab_stride = (int64_t)(c->max_hits_event > 0 ? c->max_hits_event : 1) * kTile;
   e = c->mscratch.ensure((size_t)grid * a.slab_stride * sizeof(R));
   if (e != hipSuccess) return e;
   a.mscratch = c->mscratch.p;
+  if (alloc_only) return hipSuccess;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, c->stream, a.tile_counter);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), smem, c->stream, a);
   return hipGetLastError();
+}
+
+template <typename R, int FIELD, int B>
+static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t n_tiles) {
+  return launch_scan_t<R, FIELD, B>(c, a, n_tiles, false);
+}
+
+static hipError_t dispatch_scan(rkn_ctx* c, const rkn_scan_params* p, ScanArgs& a, int64_t max_tiles,
+                                bool alloc_only) {
+  const int B = p->block_steps;
+  if (p->precision == 64)
+    return c->field_kind == 0 ? launch_scan_t<double, 0, 4>(c, a, max_tiles, alloc_only)
+                              : launch_scan_t<double, 1, 4>(c, a, max_tiles, alloc_only);
+  if (c->field_kind == 0)
+    return B == 4 ? launch_scan_t<float, 0, 4>(c, a, max_tiles, alloc_only)
+                  : launch_scan_t<float, 0, 8>(c, a, max_tiles, alloc_only);
+  return B == 4 ? launch_scan_t<float, 1, 4>(c, a, max_tiles, alloc_only)
+                : launch_scan_t<float, 1, 8>(c, a, max_tiles, alloc_only);
 }
 
 FieldDev field_dev(const rkn_ctx* c) {
@@ -452,14 +473,8 @@ FieldDev field_dev(const rkn_ctx* c) {
   return f;
 }
 
-hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
-                       const WindowDev* d_windows, const double* d_seeds5, const int64_t* d_perm,
-                       double* d_score, int32_t* d_nin, int64_t* d_best_i, double* d_best_e,
-                       const int32_t* d_ev_tiles) {
-  hipError_t e = c->parts.ensure(sizeof(ArgminPart) * (size_t)(n_tiles > 0 ? n_tiles : 1));
-  if (e != hipSuccess) return e;
-  e = c->counter.ensure(64);
-  if (e != hipSuccess) return e;
+static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_tiles, const WindowDev* d_windows,
+                          double* d_score, int32_t* d_nin) {
   ScanArgs a{};
   a.field = field_dev(c);
   a.hits32 = c->hits32.as<HitRec<float>>();
@@ -470,10 +485,7 @@ hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, co
   a.ev_maxdrift = c->ev_maxdrift.as<float>();
   a.n_layers = c->n_layers;
   a.tiles = d_tiles;
-  a.n_tiles = n_tiles;
   a.windows = d_windows;
-  a.seeds5 = d_seeds5;
-  a.perm = d_perm;
   a.tile_counter = c->counter.as<int>();
   a.R0 = p->R0;
   a.charge = p->charge;
@@ -483,22 +495,46 @@ hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, co
   a.score = d_score;
   a.nin = d_nin;
   a.parts = c->parts.as<ArgminPart>();
+  return a;
+}
+
+hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
+                       const WindowDev* d_windows, const double* d_seeds5, const int64_t* d_perm,
+                       double* d_score, int32_t* d_nin, int64_t* d_best_i, double* d_best_e,
+                       const int32_t* d_ev_tiles) {
+  hipError_t e = c->parts.ensure(sizeof(ArgminPart) * (size_t)(n_tiles > 0 ? n_tiles : 1));
+  if (e != hipSuccess) return e;
+  e = c->counter.ensure(64);
+  if (e != hipSuccess) return e;
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin);
+  a.n_tiles = n_tiles;
+  a.seeds5 = d_seeds5;
+  a.perm = d_perm;
   if (n_tiles > 0) {
-    const int B = p->block_steps;
-    if (p->precision == 64) {
-      e = c->field_kind == 0 ? launch_scan_t<double, 0, 4>(c, a, n_tiles)
-                             : launch_scan_t<double, 1, 4>(c, a, n_tiles);
-    } else if (c->field_kind == 0) {
-      e = B == 4 ? launch_scan_t<float, 0, 4>(c, a, n_tiles) : launch_scan_t<float, 0, 8>(c, a, n_tiles);
-    } else {
-      e = B == 4 ? launch_scan_t<float, 1, 4>(c, a, n_tiles) : launch_scan_t<float, 1, 8>(c, a, n_tiles);
-    }
+    e = dispatch_scan(c, p, a, n_tiles, false);
     if (e != hipSuccess) return e;
   }
   if (c->n_events > 0) {
     hipLaunchKernelGGL(event_argmin_kernel, dim3(c->n_events), dim3(256), 0, c->stream,
                        c->parts.as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_tiles, const int32_t* d_n_tiles,
+                           const Tile* d_tiles, const WindowDev* d_windows, double* d_score, int32_t* d_nin,
+                           int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only) {
+  hipError_t e = c->parts.ensure(sizeof(ArgminPart) * (size_t)(max_tiles > 0 ? max_tiles : 1));
+  if (e != hipSuccess) return e;
+  e = c->counter.ensure(64);
+  if (e != hipSuccess) return e;
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin);
+  a.n_tiles = max_tiles;
+  a.n_tiles_dev = d_n_tiles;
+  e = dispatch_scan(c, p, a, max_tiles, alloc_only);
+  if (e != hipSuccess || alloc_only) return e;
+  hipLaunchKernelGGL(event_argmin_kernel, dim3(c->n_events), dim3(256), 0, c->stream,
+                     c->parts.as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
   return hipGetLastError();
 }
 

@@ -76,6 +76,10 @@ _SIGS = {
     "rkn_scan_windows": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
     "rkn_scan_seeds": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rkn_trace": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P]),
+    "rkn_batch_plan": (C.c_int32, [_P, _P, _P]),
+    "rkn_batch_launch": (C.c_int32, [_P, _P, _P]),
+    "rkn_batch_info": (C.c_int32, [_P, _P, _P, _P, _P]),
+    "rkn_batch_results": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P, _P]),
 }
 
 _lib = None
@@ -259,6 +263,36 @@ def rkn_trace(ctx, p: rkn_scan_params, seeds5, step_idx, states=None):
     _check(ctx, load_library().rkn_trace(ctx, C.byref(p), s5.shape[0], _ptr(s5), st.size, _ptr(st),
                                          _ptr(states)))
     return states
+
+
+def rkn_batch_plan(ctx, hp: rkn_hough_params, sp: rkn_scan_params) -> None:
+    _check(ctx, load_library().rkn_batch_plan(ctx, C.byref(hp), C.byref(sp)))
+
+
+def rkn_batch_launch(ctx, best_index=None, best_score=None):
+    _check(ctx, load_library().rkn_batch_launch(ctx, _ptr(best_index), _ptr(best_score)))
+    return best_index, best_score
+
+
+def rkn_batch_info(ctx):
+    """(n_windows, n_seeds, ms_hough, ms_scan) of the last batch launch."""
+    nw = C.c_int32(); ns = C.c_int64(); th = C.c_float(); ts = C.c_float()
+    _check(ctx, load_library().rkn_batch_info(ctx, C.byref(nw), C.byref(ns), C.byref(th), C.byref(ts)))
+    return nw.value, ns.value, th.value, ts.value
+
+
+def rkn_batch_results(ctx, n_events: int, want_scores: bool = True):
+    """(windows, scores, n_in, ev_seed_off) of the last batch launch (host arrays)."""
+    nw, ns, _, _ = rkn_batch_info(ctx)
+    arr = (rkn_window * max(nw, 1))()
+    score = np.zeros(max(ns, 1)) if want_scores else None
+    nin = np.zeros(max(ns, 1), np.int32) if want_scores else None
+    off = np.zeros(n_events + 1, np.int64)
+    n = C.c_int32()
+    _check(ctx, load_library().rkn_batch_results(ctx, nw, arr, C.byref(n), ns, _ptr(score), _ptr(nin),
+                                                 _ptr(off)))
+    return windows_from_c(arr, n.value), (score[:ns] if want_scores else None), \
+        (nin[:ns] if want_scores else None), off
 
 
 class Context:

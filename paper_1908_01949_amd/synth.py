@@ -597,18 +597,18 @@ def event_fixed_total(geo: Geometry, field: Field, seed: int, n_total: int = 150
 def events_batch(geo: Geometry, field: Field, n_events: int = 512, seed: int = 0,
                  n_steps: int = 6000, sigma: float = 0.2, hits_range=(40, 300),
                  noise_range=(0.1, 0.4), p_range=(60.0, 105.0), max_tracks: int = 3,
-                 tracks_cache: list | None = None) -> list[Event]:
+                 pool_size: int = 256, truth_step: float = 1.0) -> list[Event]:
     """Many events: 1-3 e- with p ~ U[60,105] MeV/c, 40-300 hits, 10-40 % noise.
 
-    Tracks are drawn first (and may be reused across calls through tracks_cache),
-    then each event takes its tracks and hit budget from its own generator.
+    A pool of accepted truth tracks (reaching the chamber, >= 40 true hits) is traced
+    once, vectorised; each event then draws its tracks from the pool and its hit
+    budget from its own generator.
     """
     rng = np.random.default_rng([BASE_SEED, 4, seed])
     tf = TruthField(field)
-    pool = tracks_cache if tracks_cache is not None else []
-    need = n_events * max_tracks
-    while len(pool) < need:
-        k = 64
+    pool = []
+    while len(pool) < pool_size:
+        k = 2 * pool_size
         pm = rng.uniform(*p_range, k)
         pz = rng.uniform(-25.0, 25.0, k)
         pz = np.clip(pz, -0.5 * pm, 0.5 * pm)
@@ -616,11 +616,11 @@ def events_batch(geo: Geometry, field: Field, n_events: int = 512, seed: int = 0
         ph = 2 * np.pi * rng.random(k)
         pv = np.stack([pt * np.cos(ph), pt * np.sin(ph), pz], -1)
         v = _draw_vertex(rng, k)
-        for tr, pmi in zip(trace_truth(tf, v, pv, ELECTRON_Q, n_steps - 20.0), pm):
-            if tr is None:
+        for tr, pmi in zip(trace_truth(tf, v, pv, ELECTRON_Q, n_steps - 20.0, h=truth_step), pm):
+            if tr is None or len(pool) >= pool_size:
                 continue
             w, d, s = true_wire_distances(geo, tr, n_steps - 20.0)
-            if w.size >= 30:
+            if w.size >= 40:
                 pool.append((tr.seed, float(pmi), w, d))
     events = []
     for e in range(n_events):
@@ -644,7 +644,8 @@ def events_batch(geo: Geometry, field: Field, n_events: int = 512, seed: int = 0
         wires = np.array(list(chosen.keys()), dtype=np.int32)
         dists = np.array([chosen[w][0] for w in wires])
         tro = np.array([chosen[w][1] for w in wires], dtype=np.int32)
-        n_noise = n_total - wires.size
+        # keep the drawn noise fraction when the tracks give fewer true hits than asked
+        n_noise = n_noise if wires.size == n_true else int(round(f / (1.0 - f) * wires.size))
         events.append(_finish_event(er, geo, wires, dists, tro, [pool[i][0] for i in picks],
                                     [pool[i][1] for i in picks], n_noise, sigma))
     return events

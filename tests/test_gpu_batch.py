@@ -1,0 +1,84 @@
+"""GPU parity of the batched path: Hough windows -> tiles -> one persistent scan launch
+-> per-event argmin, replayed from captured HIP graphs."""
+import numpy as np
+import pytest
+
+from paper_1908_01949_amd import synth
+from tests import parity_util as pu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rk():
+    from paper_1908_01949_amd import rknscan
+    rknscan.load_library()
+    return rknscan
+
+
+def test_batch_matches_oracle_and_replays(rk, geo, sfield, orc_s):
+    evs = synth.events_batch(geo, sfield, 12, seed=1, pool_size=24)
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    kw = dict(b_ref=sfield.b_ref, max_cand=3, gran=(0.01, 100.0, 2.5, 2.5, 12.0), count=(3, 2, 3, 3, 2),
+              grow=(1, 0, 1, 1, 0), count_max=5, max_seeds_window=200)
+    hp = rk.make_hough_params(**kw)
+    n_steps = 1500
+    sp = rk.make_scan_params(n_steps=n_steps, precision=32)
+    rk.rkn_batch_plan(c.ctx, hp, sp)
+    ne = len(evs)
+    bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+    rk.rkn_batch_launch(c.ctx, bi, bs)
+    nw, ns, th, ts = rk.rkn_batch_info(c.ctx)
+    print(f"batch: {nw} windows, {ns} seeds, hough {th:.2f} ms, scan {ts:.2f} ms", flush=True)
+    w, score, nin, ev_seed = rk.rkn_batch_results(c.ctx, ne)
+    assert nw >= ne and ns == int(sum(np.prod(x["count"].astype(np.int64)) for x in w))
+    # windows: the batch expansion keeps exactly the Hough stage's windows
+    w_direct = rk.rkn_hough_seed_windows(c.ctx, hp)
+    assert np.array_equal(w_direct, w)
+    ow = orc_s.hough_seed_windows(orc_s.hough_params(**kw), off, wid)
+    assert np.array_equal(ow["count"], w["count"]) and np.array_equal(ow["event"], w["event"])
+    np.testing.assert_allclose(ow["center"], w["center"], rtol=0, atol=1e-11)
+    # scores against the oracle on the same windows
+    osc, onin, obi, obs, _ = orc_s.scan_windows(orc_s.params(n_steps=n_steps), off, wid, dr, w)
+    rel = pu.check_scores(score, osc)
+    print(f"max rel score error {rel:.2e}", flush=True)
+    pu.check_nin(nin, onin)
+    for e in range(ne):
+        lo, hi = ev_seed[e], ev_seed[e + 1]
+        if hi > lo:
+            pu.check_best(bi[e], osc[lo:hi], offset=lo)
+        else:
+            assert bi[e] == -1
+    # same kernels as the eager scan: bit-identical scores
+    s2 = np.zeros(ns); n2 = np.zeros(ns, np.int32); b2 = np.zeros(ne, np.int64); e2 = np.zeros(ne)
+    rk.rkn_scan_windows(c.ctx, sp, w, s2, n2, b2, e2)
+    assert np.array_equal(s2, score) and np.array_equal(b2, bi)
+    # replays after other work give identical results
+    for _ in range(3):
+        bi3 = np.zeros(ne, np.int64); bs3 = np.zeros(ne)
+        rk.rkn_batch_launch(c.ctx, bi3, bs3)
+        _, s3, _, _ = rk.rkn_batch_results(c.ctx, ne)
+        assert np.array_equal(s3, score) and np.array_equal(bi3, bi) and np.array_equal(bs3, bs)
+        rk.rkn_scan_windows(c.ctx, sp, w[:2], None, None, np.zeros(ne, np.int64), np.zeros(ne))
+    c.close()
+
+
+def test_batch_requires_plan_and_reupload_invalidates(rk, geo, ufield):
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(ufield)
+    ev = synth.event_single_turn(geo, ufield, 0)
+    off, wid, dr = synth.pack_events([ev])
+    c.upload_hits(off, wid, dr)
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_batch_launch(c.ctx, np.zeros(1, np.int64), np.zeros(1))
+    assert e.value.status == rk.RKN_E_STATE
+    rk.rkn_batch_plan(c.ctx, rk.make_hough_params(count=(2, 2, 2, 2, 2), count_max=2),
+                      rk.make_scan_params(n_steps=300))
+    rk.rkn_batch_launch(c.ctx, np.zeros(1, np.int64), np.zeros(1))
+    c.upload_hits(off, wid, dr)
+    with pytest.raises(rk.RknError) as e:
+        rk.rkn_batch_launch(c.ctx, np.zeros(1, np.int64), np.zeros(1))
+    assert e.value.status == rk.RKN_E_STATE
+    c.close()

@@ -237,6 +237,24 @@ def test_band_pruning_bit_identical(geo, ufield, sfield, cfg):
         assert pp < pb
 
 
+@pytest.mark.parametrize("block", [4, 8])
+def test_block_pruning_bit_identical(geo, ufield, sfield, block):
+    """The kernel's two-level block pruning gives bit-identical E and n_in, with far fewer pairs."""
+    import oracle
+    for f, ev in ((ufield, synth.event_multi_turn(geo, ufield, 5)),
+                  (sfield, synth.event_fixed_total(geo, sfield, 1))):
+        O = oracle.Oracle(geo, f)
+        prm = O.params(n_steps=2999)
+        rng = np.random.default_rng(12)
+        seeds = synth.random_seeds(rng, ev.truth_seeds[0], [0.2, 60, 8, 8, 8], 10)
+        seeds[0] = ev.truth_seeds[0]
+        for s in seeds:
+            Eb, nb, pb = O.score(prm, s, ev.wire_id, ev.drift, mode=0)
+            Ek, nk, cull, pk = O.score_blocked(prm, s, ev.wire_id, ev.drift, block=block)
+            assert Eb == Ek and nb == nk
+            assert pk < pb / 5 and cull < pb
+
+
 # ---------------------------------------------------------------------------------------
 # argmin over a small grid through an independent evaluation path
 # ---------------------------------------------------------------------------------------
