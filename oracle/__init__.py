@@ -74,6 +74,9 @@ def lib():
         _lib.orc_score.argtypes = [P, P, P, P, C.c_int32, P, P, C.c_int32, P, P]
         _lib.orc_score_blocked.restype = C.c_double
         _lib.orc_score_blocked.argtypes = [P, P, P, P, C.c_int32, P, P, C.c_int32, P, P, P]
+        _lib.orc_inlier_mask.argtypes = [P, P, P, P, C.c_int32, P, P, P]
+        _lib.orc_residual_jacobian.argtypes = [P, P, P, P, C.c_int32, P, P, P, P, P]
+        _lib.orc_gn_refine.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int32, P, P, P]
         _lib.orc_seg_wire_dist2.restype = C.c_double
         _lib.orc_seg_wire_dist2.argtypes = [P, P, P, P, C.c_double]
         _lib.orc_field_eval.argtypes = [P, P, P]
@@ -173,6 +176,30 @@ class Oracle:
         E = lib().orc_score_blocked(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size,
                                     _ptr(w), _ptr(d), int(block), C.byref(n_in), C.byref(cull), C.byref(pairs))
         return E, n_in.value, cull.value, pairs.value
+
+    # ---- refinement ----------------------------------------------------------------
+    def inlier_mask(self, prm, seed, wire_id, drift):
+        s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
+        d = np.ascontiguousarray(drift, np.float32); m = np.zeros(w.size, np.uint8)
+        lib().orc_inlier_mask(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size, _ptr(w),
+                              _ptr(d), _ptr(m))
+        return m
+
+    def residual_jacobian(self, prm, seed, wire_id, drift, mask):
+        s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
+        d = np.ascontiguousarray(drift, np.float32); m = np.ascontiguousarray(mask, np.uint8)
+        r = np.zeros(w.size); J = np.zeros((w.size, 5))
+        ok = lib().orc_residual_jacobian(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size,
+                                         _ptr(w), _ptr(d), _ptr(m), _ptr(r), _ptr(J))
+        return bool(ok), r, J
+
+    def gn_refine(self, prm, seed, wire_id, drift, scale=(1.0, 100.0, 100.0, 100.0, 100.0), iters=10):
+        s = np.array(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
+        d = np.ascontiguousarray(drift, np.float32); m = np.zeros(w.size, np.uint8)
+        sc = np.ascontiguousarray(scale, np.float64); phi = np.zeros(iters + 1)
+        lib().orc_gn_refine(C.byref(self.geo), C.byref(self.field), C.byref(prm), w.size, _ptr(w), _ptr(d),
+                            _ptr(sc), int(iters), _ptr(s), _ptr(m), _ptr(phi))
+        return s, m, phi
 
     @staticmethod
     def window_struct(w) -> OrcWindow:

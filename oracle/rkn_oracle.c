@@ -150,8 +150,19 @@ static double f_at(const double r[3], const double d[3], const double u[3], doub
 }
 static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+static double seg_wire_best(const double p0[3], const double p1[3], const double m[3], const double u[3],
+                            double L, double *s_best, double *t_best);
+
 double orc_seg_wire_dist2(const double p0[3], const double p1[3], const double m[3],
                           const double u[3], double L) {
+  double sb, tb;
+  return seg_wire_best(p0, p1, m, u, L, &sb, &tb);
+}
+
+/* Same minimum, also returning the minimising parameters (s on the chord, t on the
+ * wire). Candidates are tried in a fixed order; the first smallest one wins.     */
+static double seg_wire_best(const double p0[3], const double p1[3], const double m[3], const double u[3],
+                            double L, double *s_best, double *t_best) {
   double r[3] = {p0[0] - m[0], p0[1] - m[1], p0[2] - m[2]};
   double d[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
   double a = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -161,30 +172,35 @@ double orc_seg_wire_dist2(const double p0[3], const double p1[3], const double m
   double g = u[0] * r[0] + u[1] * r[1] + u[2] * r[2];
   double best = INFINITY, v, s, t;
   double det = a * c - b * b;
+#define ORC_TAKE(S, T)              \
+  do {                              \
+    v = f_at(r, d, u, (S), (T));    \
+    if (v < best) {                 \
+      best = v;                     \
+      *s_best = (S);                \
+      *t_best = (T);                \
+    }                               \
+  } while (0)
+  *s_best = 0.0;
+  *t_best = 0.0;
   if (det > 1e-14 * a * c) {          /* non-parallel: interior stationary point */
     s = (b * g - c * e) / det;
     t = (a * g - b * e) / det;
-    if (s >= 0.0 && s <= 1.0 && t >= -L && t <= L) {
-      v = f_at(r, d, u, s, t);
-      if (v < best) best = v;
-    }
+    if (s >= 0.0 && s <= 1.0 && t >= -L && t <= L) ORC_TAKE(s, t);
   }
   /* edges s = 0 and s = 1: minimise over t */
   t = clampd(g / c, -L, L);
-  v = f_at(r, d, u, 0.0, t);
-  if (v < best) best = v;
+  ORC_TAKE(0.0, t);
   t = clampd((g + b) / c, -L, L);
-  v = f_at(r, d, u, 1.0, t);
-  if (v < best) best = v;
+  ORC_TAKE(1.0, t);
   /* edges t = -L and t = +L: minimise over s */
   if (a > 0.0) {
     s = clampd(-(e + L * b) / a, 0.0, 1.0);
-    v = f_at(r, d, u, s, -L);
-    if (v < best) best = v;
+    ORC_TAKE(s, -L);
     s = clampd(-(e - L * b) / a, 0.0, 1.0);
-    v = f_at(r, d, u, s, L);
-    if (v < best) best = v;
+    ORC_TAKE(s, L);
   }
+#undef ORC_TAKE
   return best;
 }
 
@@ -705,4 +721,302 @@ int orc_hough_seed_windows(const orc_geometry *g, const orc_hough_params *hp, in
   }
   free(acc); free(pf); free(pc);
   return n <= max_windows ? n : -n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Refinement (not in the paper, whose refinement is the rescan of finer grids in
+ * section 2.2): Gauss-Newton on Phi(s) = sum over the inlier set S of (D_i - d_i)^2,
+ * with S fixed by the classification rule (D - d)^2 < lambda at the starting seed.
+ * Derivatives are those of the discrete map (differentiate the RKN steps as
+ * computed). D_i is the minimum over chords; by the envelope theorem its gradient
+ * is that of the minimising chord's distance at its minimising parameters:
+ * dD/dx_n = (1 - s*) w and dD/dx_{n+1} = s* w, w the unit closest-approach vector.
+ * FP64 forward sensitivities: Y_n = d(x_n, T_n, Lambda)/d(seed) (7 x 5) carried
+ * through every stage of the step by the chain rule.                            */
+
+/* Field and its Jacobian dB/dx (row c = component, column k = d/dx_k). */
+static void field_jac(const orc_field *f, const double x[3], double B[3], double J[3][3]) {
+  int c, k;
+  for (c = 0; c < 3; ++c)
+    for (k = 0; k < 3; ++k) J[c][k] = 0.0;
+  if (f->kind == 0) {
+    B[0] = 0.0; B[1] = 0.0; B[2] = f->bz;
+    return;
+  }
+  {
+    double r = sqrt(x[0] * x[0] + x[1] * x[1]);
+    double dr = (f->r1 - f->r0) / (double)(f->nr - 1), dz = (f->z1 - f->z0) / (double)(f->nz - 1);
+    double u = (r - f->r0) / dr, v = (x[2] - f->z0) / dz;
+    int i = (int)floor(u), j = (int)floor(v), ui = 1, vi = 1;   /* ui/vi: inside (not clamped) */
+    double a, b, q00r, q01r, q10r, q11r, q00z, q01z, q10z, q11z, br, bz, dbr_dr, dbr_dz, dbz_dr, dbz_dz;
+    if (i < 0) i = 0;
+    if (i > f->nr - 2) i = f->nr - 2;
+    if (j < 0) j = 0;
+    if (j > f->nz - 2) j = f->nz - 2;
+    a = u - i;
+    b = v - j;
+    if (a < 0.0) { a = 0.0; ui = 0; }
+    if (a > 1.0) { a = 1.0; ui = 0; }
+    if (b < 0.0) { b = 0.0; vi = 0; }
+    if (b > 1.0) { b = 1.0; vi = 0; }
+    q00r = f->br[j * f->nr + i]; q01r = f->br[j * f->nr + i + 1];
+    q10r = f->br[(j + 1) * f->nr + i]; q11r = f->br[(j + 1) * f->nr + i + 1];
+    q00z = f->bzg[j * f->nr + i]; q01z = f->bzg[j * f->nr + i + 1];
+    q10z = f->bzg[(j + 1) * f->nr + i]; q11z = f->bzg[(j + 1) * f->nr + i + 1];
+    br = (1.0 - b) * ((1.0 - a) * q00r + a * q01r) + b * ((1.0 - a) * q10r + a * q11r);
+    bz = (1.0 - b) * ((1.0 - a) * q00z + a * q01z) + b * ((1.0 - a) * q10z + a * q11z);
+    dbr_dr = ui ? ((1.0 - b) * (q01r - q00r) + b * (q11r - q10r)) / dr : 0.0;
+    dbz_dr = ui ? ((1.0 - b) * (q01z - q00z) + b * (q11z - q10z)) / dr : 0.0;
+    dbr_dz = vi ? (((1.0 - a) * q10r + a * q11r) - ((1.0 - a) * q00r + a * q01r)) / dz : 0.0;
+    dbz_dz = vi ? (((1.0 - a) * q10z + a * q11z) - ((1.0 - a) * q00z + a * q01z)) / dz : 0.0;
+    B[2] = bz;
+    if (r < 1e-9) {
+      B[0] = 0.0; B[1] = 0.0;
+      /* on the axis B_r = r dB_r/dr to first order: B_x = dbr_dr x, B_y = dbr_dr y */
+      J[0][0] = dbr_dr; J[1][1] = dbr_dr;
+      J[2][2] = dbz_dz;
+    } else {
+      double cx = x[0] / r, cy = x[1] / r;
+      B[0] = br * cx;
+      B[1] = br * cy;
+      /* d(r)/dx = cx, dr/dy = cy; d(cx)/dx = (1 - cx^2)/r, d(cx)/dy = -cx cy / r, ... */
+      J[0][0] = dbr_dr * cx * cx + br * (1.0 - cx * cx) / r;
+      J[0][1] = dbr_dr * cx * cy - br * cx * cy / r;
+      J[0][2] = dbr_dz * cx;
+      J[1][0] = dbr_dr * cy * cx - br * cx * cy / r;
+      J[1][1] = dbr_dr * cy * cy + br * (1.0 - cy * cy) / r;
+      J[1][2] = dbr_dz * cy;
+      J[2][0] = dbz_dr * cx;
+      J[2][1] = dbz_dr * cy;
+      J[2][2] = dbz_dz;
+    }
+  }
+}
+
+static void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* k = Lam T x B(xp) and its tangent for each of the 5 columns: dk = dLam T x B +
+ * Lam dT x B + Lam T x (J dxp). */
+static void stage_tan(const orc_field *f, double Lam, const double xp[3], const double T[3],
+                      double dLam[5], double dxp[3][5], double dT[3][5], double k[3], double dk[3][5]) {
+  double B[3], J[3][3], TB[3];
+  int c, q;
+  field_jac(f, xp, B, J);
+  cross3(T, B, TB);
+  for (c = 0; c < 3; ++c) k[c] = Lam * TB[c];
+  for (q = 0; q < 5; ++q) {
+    double dTq[3] = {dT[0][q], dT[1][q], dT[2][q]}, dB[3], t1[3], t2[3];
+    for (c = 0; c < 3; ++c) dB[c] = J[c][0] * dxp[0][q] + J[c][1] * dxp[1][q] + J[c][2] * dxp[2][q];
+    cross3(dTq, B, t1);
+    cross3(T, dB, t2);
+    for (c = 0; c < 3; ++c) dk[c][q] = dLam[q] * TB[c] + Lam * (t1[c] + t2[c]);
+  }
+}
+
+/* One RKN step (the same arithmetic as orc_rkn_step) with the tangents Y of
+ * (x, T) and the constant dLam carried along. */
+static void rkn_step_tan(const orc_field *f, double Lam, double h, double x[3], double T[3], double Y[6][5],
+                         double dLam[5]) {
+  double k1[3], k2[3], k3[3], k4[3], xm[3], xe[3], Tt[3];
+  double dk1[3][5], dk2[3][5], dk3[3][5], dk4[3][5], dxm[3][5], dxe[3][5], dTt[3][5], dx[3][5], dT[3][5];
+  int c, q;
+  for (c = 0; c < 3; ++c)
+    for (q = 0; q < 5; ++q) {
+      dx[c][q] = Y[c][q];
+      dT[c][q] = Y[3 + c][q];
+    }
+  stage_tan(f, Lam, x, T, dLam, dx, dT, k1, dk1);
+  for (c = 0; c < 3; ++c) {
+    xm[c] = x[c] + 0.5 * h * T[c] + 0.125 * h * h * k1[c];
+    Tt[c] = T[c] + 0.5 * h * k1[c];
+    for (q = 0; q < 5; ++q) {
+      dxm[c][q] = dx[c][q] + 0.5 * h * dT[c][q] + 0.125 * h * h * dk1[c][q];
+      dTt[c][q] = dT[c][q] + 0.5 * h * dk1[c][q];
+    }
+  }
+  stage_tan(f, Lam, xm, Tt, dLam, dxm, dTt, k2, dk2);
+  for (c = 0; c < 3; ++c) {
+    Tt[c] = T[c] + 0.5 * h * k2[c];
+    for (q = 0; q < 5; ++q) dTt[c][q] = dT[c][q] + 0.5 * h * dk2[c][q];
+  }
+  stage_tan(f, Lam, xm, Tt, dLam, dxm, dTt, k3, dk3);
+  for (c = 0; c < 3; ++c) {
+    xe[c] = x[c] + h * T[c] + 0.5 * h * h * k3[c];
+    Tt[c] = T[c] + h * k3[c];
+    for (q = 0; q < 5; ++q) {
+      dxe[c][q] = dx[c][q] + h * dT[c][q] + 0.5 * h * h * dk3[c][q];
+      dTt[c][q] = dT[c][q] + h * dk3[c][q];
+    }
+  }
+  stage_tan(f, Lam, xe, Tt, dLam, dxe, dTt, k4, dk4);
+  for (c = 0; c < 3; ++c) {
+    x[c] = x[c] + h * T[c] + (h * h / 6.0) * (k1[c] + k2[c] + k3[c]);
+    T[c] = T[c] + (h / 6.0) * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+    for (q = 0; q < 5; ++q) {
+      Y[c][q] = dx[c][q] + h * dT[c][q] + (h * h / 6.0) * (dk1[c][q] + dk2[c][q] + dk3[c][q]);
+      Y[3 + c][q] = dT[c][q] + (h / 6.0) * (dk1[c][q] + 2.0 * dk2[c][q] + 2.0 * dk3[c][q] + dk4[c][q]);
+    }
+  }
+}
+
+/* Residuals r_i = D_i - d_i and their Jacobian J_i = dr_i/d(seed) for the hits
+ * with mask[i] != 0 (others: r and J set to 0). Returns 0 if |p| is too small. */
+int orc_residual_jacobian(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+                          int32_t n_hits, const int32_t *wire_id, const float *drift, const uint8_t *mask,
+                          double *resid, double *jac /* [n_hits][5] */) {
+  double x[3], T[3], Lam, xo[3], Y[6][5], Yo[6][5], dLam[5], pm;
+  double *d2 = (double *)malloc(sizeof(double) * (n_hits > 0 ? n_hits : 1));
+  int32_t i, n, c, q;
+  for (i = 0; i < n_hits; ++i) {
+    d2[i] = INFINITY;
+    resid[i] = 0.0;
+    for (q = 0; q < 5; ++q) jac[5 * i + q] = 0.0;
+  }
+  if (!orc_seed_state(p, seed, x, T, &Lam)) {
+    free(d2);
+    return 0;
+  }
+  pm = sqrt(seed[2] * seed[2] + seed[3] * seed[3] + seed[4] * seed[4]);
+  /* Y0 = d(x0, T0)/d(theta, z0, px, py, pz); dLam/dp_j = -Lam T_j / |p| */
+  for (c = 0; c < 6; ++c)
+    for (q = 0; q < 5; ++q) Y[c][q] = 0.0;
+  Y[0][0] = -p->R0 * sin(seed[0]);
+  Y[1][0] = p->R0 * cos(seed[0]);
+  Y[2][1] = 1.0;
+  for (c = 0; c < 3; ++c)
+    for (q = 0; q < 3; ++q) Y[3 + c][2 + q] = ((c == q ? 1.0 : 0.0) - T[c] * T[q]) / pm;
+  dLam[0] = 0.0;
+  dLam[1] = 0.0;
+  for (q = 0; q < 3; ++q) dLam[2 + q] = -Lam * T[q] / pm;
+  for (n = 0; n < p->n_steps; ++n) {
+    xo[0] = x[0]; xo[1] = x[1]; xo[2] = x[2];
+    memcpy(Yo, Y, sizeof(Y));
+    rkn_step_tan(f, Lam, p->step_mm, x, T, Y, dLam);
+    for (i = 0; i < n_hits; ++i) {
+      double m[3], u[3], L, v, sb, tb;
+      if (!mask[i]) continue;
+      wire_of(g, wire_id[i], m, u, &L);
+      v = seg_wire_best(xo, x, m, u, L, &sb, &tb);
+      if (v < d2[i]) {
+        double w[3], D = sqrt(v);
+        d2[i] = v;
+        for (c = 0; c < 3; ++c) w[c] = xo[c] + sb * (x[c] - xo[c]) - (m[c] + tb * u[c]);
+        resid[i] = D - (double)drift[i];
+        for (q = 0; q < 5; ++q) {
+          double acc = 0.0;
+          if (D > 0.0)
+            for (c = 0; c < 3; ++c) acc += (w[c] / D) * ((1.0 - sb) * Yo[c][q] + sb * Y[c][q]);
+          jac[5 * i + q] = acc;
+        }
+      }
+    }
+  }
+  free(d2);
+  return 1;
+}
+
+/* Inlier mask at a seed: (D - d)^2 < lambda (brute-force D). */
+int orc_inlier_mask(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+                    int32_t n_hits, const int32_t *wire_id, const float *drift, uint8_t *mask) {
+  double *d2 = (double *)malloc(sizeof(double) * (n_hits > 0 ? n_hits : 1));
+  int32_t i, ok = orc_doca2(g, f, p, seed, n_hits, wire_id, d2);
+  for (i = 0; i < n_hits; ++i) {
+    double r = sqrt(d2[i]) - (double)drift[i];
+    mask[i] = (uint8_t)(ok && r * r < p->lambda_mm2);
+  }
+  free(d2);
+  return ok;
+}
+
+static double phi_of(const double *resid, const uint8_t *mask, int32_t n) {
+  double s = 0.0;
+  int32_t i;
+  for (i = 0; i < n; ++i)
+    if (mask[i]) s += resid[i] * resid[i];
+  return s;
+}
+
+/* Solve A x = b for a symmetric positive-definite 5x5 A (Cholesky); returns 0 if A
+ * is not positive definite. */
+static int chol5(const double A[5][5], const double b[5], double x[5]) {
+  double Lm[5][5] = {{0}}, y[5];
+  int i, j, k;
+  for (i = 0; i < 5; ++i) {
+    for (j = 0; j <= i; ++j) {
+      double s = A[i][j];
+      for (k = 0; k < j; ++k) s -= Lm[i][k] * Lm[j][k];
+      if (i == j) {
+        if (!(s > 0.0)) return 0;
+        Lm[i][i] = sqrt(s);
+      } else {
+        Lm[i][j] = s / Lm[j][j];
+      }
+    }
+  }
+  for (i = 0; i < 5; ++i) {
+    double s = b[i];
+    for (k = 0; k < i; ++k) s -= Lm[i][k] * y[k];
+    y[i] = s / Lm[i][i];
+  }
+  for (i = 4; i >= 0; --i) {
+    double s = y[i];
+    for (k = i + 1; k < 5; ++k) s -= Lm[k][i] * x[k];
+    x[i] = s / Lm[i][i];
+  }
+  return 1;
+}
+
+/* Gauss-Newton refinement: the normal equations (J^T J) delta = -J^T r in the
+ * scaled variables delta' = D delta, D = diag(scale), solved in FP64 by Cholesky
+ * (with mu = 1e-12 trace added if not positive definite); a step is accepted at the
+ * first of alpha = 1, 1/2, ..., 1/32 that lowers Phi, otherwise the seed stays.
+ * Exactly `iters` iterations; phi receives Phi before each and after the last. */
+int orc_gn_refine(const orc_geometry *g, const orc_field *f, const orc_params *p, int32_t n_hits,
+                  const int32_t *wire_id, const float *drift, const double scale[5], int32_t iters,
+                  double seed[5], uint8_t *mask, double *phi) {
+  double *r = (double *)malloc(sizeof(double) * (n_hits > 0 ? n_hits : 1));
+  double *J = (double *)malloc(sizeof(double) * 5 * (n_hits > 0 ? n_hits : 1));
+  double *rt = (double *)malloc(sizeof(double) * (n_hits > 0 ? n_hits : 1));
+  double *Jt = (double *)malloc(sizeof(double) * 5 * (n_hits > 0 ? n_hits : 1));
+  int32_t it, i, a, b, k;
+  double cur;
+  orc_inlier_mask(g, f, p, seed, n_hits, wire_id, drift, mask);
+  orc_residual_jacobian(g, f, p, seed, n_hits, wire_id, drift, mask, r, J);
+  cur = phi_of(r, mask, n_hits);
+  for (it = 0; it < iters; ++it) {
+    double A[5][5] = {{0}}, rhs[5] = {0}, dlt[5], tr = 0.0;
+    phi[it] = cur;
+    for (i = 0; i < n_hits; ++i) {
+      if (!mask[i]) continue;
+      for (a = 0; a < 5; ++a) {
+        rhs[a] -= J[5 * i + a] * scale[a] * r[i];
+        for (b = 0; b < 5; ++b) A[a][b] += J[5 * i + a] * scale[a] * J[5 * i + b] * scale[b];
+      }
+    }
+    for (a = 0; a < 5; ++a) tr += A[a][a];
+    if (!chol5(A, rhs, dlt)) {
+      for (a = 0; a < 5; ++a) A[a][a] += 1e-12 * tr;
+      if (!chol5(A, rhs, dlt)) continue;
+    }
+    for (k = 0; k < 6; ++k) {
+      double alpha = ldexp(1.0, -k), trial[5], ph;
+      for (a = 0; a < 5; ++a) trial[a] = seed[a] + alpha * dlt[a] * scale[a];
+      if (!orc_residual_jacobian(g, f, p, trial, n_hits, wire_id, drift, mask, rt, Jt)) continue;
+      ph = phi_of(rt, mask, n_hits);
+      if (ph < cur) {
+        memcpy(seed, trial, sizeof(trial));
+        memcpy(r, rt, sizeof(double) * n_hits);
+        memcpy(J, Jt, sizeof(double) * 5 * n_hits);
+        cur = ph;
+        break;
+      }
+    }
+  }
+  phi[iters] = cur;
+  free(r); free(J); free(rt); free(Jt);
+  return 0;
 }

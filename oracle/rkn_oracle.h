@@ -132,6 +132,16 @@ int orc_hough_seed_windows(const orc_geometry *g, const orc_hough_params *hp, in
                            const int32_t *ev_off, const int32_t *wire_id, int32_t max_windows,
                            orc_window *out);
 
+/* ---- Refinement (Gauss-Newton on the inlier residuals; FP64 forward sensitivities) ---- */
+int orc_inlier_mask(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+                    int32_t n_hits, const int32_t *wire_id, const float *drift, uint8_t *mask);
+int orc_residual_jacobian(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
+                          int32_t n_hits, const int32_t *wire_id, const float *drift, const uint8_t *mask,
+                          double *resid, double *jac /* [n_hits][5] */);
+int orc_gn_refine(const orc_geometry *g, const orc_field *f, const orc_params *p, int32_t n_hits,
+                  const int32_t *wire_id, const float *drift, const double scale[5], int32_t iters,
+                  double seed[5], uint8_t *mask, double *phi /* [iters+1] */);
+
 #ifdef __cplusplus
 }
 #endif

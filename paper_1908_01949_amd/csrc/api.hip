@@ -103,6 +103,12 @@ rkn_status rkn_create(int32_t device, void* hip_stream, rkn_ctx** out) {
     delete c;
     return RKN_E_DEVICE;
   }
+  int lds = 0, lds_optin = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    c->max_lds_block = lds;
+  if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
+      lds_optin > c->max_lds_block)
+    c->max_lds_block = lds_optin;
   if (hip_stream) {
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   } else {
@@ -359,6 +365,7 @@ rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_wind
   std::vector<rkn::WindowDev> wins(std::max(n_windows, 1));
   std::vector<rkn::Tile> tiles;
   std::vector<int32_t> ev_tiles(c->n_events + 1, 0);
+  const int T = rkn::scan_tile(c, p);
   int64_t total = 0;
   int last_ev = -1;
   for (int k = 0; k < n_windows; ++k) {
@@ -382,11 +389,11 @@ rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_wind
       d.count[j] = x.count[j];
     }
     d.event = x.event;
-    for (int64_t s = 0; s < size; s += rkn::kTile) {
+    for (int64_t s = 0; s < size; s += T) {
       rkn::Tile t{};
       t.window = k;
       t.event = x.event;
-      t.n = (int32_t)std::min<int64_t>(rkn::kTile, size - s);
+      t.n = (int32_t)std::min<int64_t>(T, size - s);
       t.start = s;
       t.gbase = total + s;
       tiles.push_back(t);
@@ -433,6 +440,7 @@ rkn_status rkn_scan_seeds(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds,
   std::vector<rkn::WindowDev> wins(1);
   std::vector<rkn::Tile> tiles;
   std::vector<int32_t> ev_tiles(c->n_events + 1, 0);
+  const int T = rkn::scan_tile(c, p);
   int last_ev = -1;
   for (int64_t i = 0; i < n_seeds;) {
     const int ev = seed_event[order[i]];
@@ -440,11 +448,11 @@ rkn_status rkn_scan_seeds(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds,
     while (j < n_seeds && seed_event[order[j]] == ev) ++j;
     for (int e = last_ev + 1; e <= ev; ++e) ev_tiles[e] = (int32_t)tiles.size();
     last_ev = ev;
-    for (int64_t s = i; s < j; s += rkn::kTile) {
+    for (int64_t s = i; s < j; s += T) {
       rkn::Tile t{};
       t.window = 0;
       t.event = ev;
-      t.n = (int32_t)std::min<int64_t>(rkn::kTile, j - s);
+      t.n = (int32_t)std::min<int64_t>(T, j - s);
       t.start = s;
       t.gbase = s;
       tiles.push_back(t);

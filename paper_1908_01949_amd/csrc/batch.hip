@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256)
 batch_expand_kernel(const WinSlot* __restrict__ slots, const int32_t* __restrict__ nsel, int n_events,
                     int32_t* __restrict__ ev_nw, int32_t* __restrict__ ev_nt, long long* __restrict__ ev_ns,
                     WindowDev* __restrict__ windows, Tile* __restrict__ tiles, int32_t* __restrict__ ev_tiles,
-                    long long* __restrict__ ev_seed, int32_t* __restrict__ counts) {
+                    long long* __restrict__ ev_seed, int32_t* __restrict__ counts, int tile) {
   const int tid = threadIdx.x;
   for (int e = tid; e < n_events; e += 256) {
     int nw = 0, nt = 0;
@@ -33,7 +33,7 @@ batch_expand_kernel(const WinSlot* __restrict__ slots, const int32_t* __restrict
       long long size = 1;
       for (int q = 0; q < 5; ++q) size *= s.w.count[q];
       ++nw;
-      nt += (int)((size + kTile - 1) / kTile);
+      nt += (int)((size + tile - 1) / tile);
       ns += size;
     }
     ev_nw[e] = nw;
@@ -69,11 +69,11 @@ batch_expand_kernel(const WinSlot* __restrict__ slots, const int32_t* __restrict
       long long size = 1;
       for (int q = 0; q < 5; ++q) size *= s.w.count[q];
       windows[w] = s.w;
-      for (long long st = 0; st < size; st += kTile) {
+      for (long long st = 0; st < size; st += tile) {
         Tile tl;
         tl.window = w;
         tl.event = e;
-        tl.n = (int32_t)(size - st < kTile ? size - st : kTile);
+        tl.n = (int32_t)(size - st < tile ? size - st : tile);
         tl.pad = 0;
         tl.start = st;
         tl.gbase = g + st;
@@ -149,7 +149,10 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
                                                                     h.count_max * h.count_max * h.count_max);
   const int64_t max_windows = (int64_t)ne * h.max_cand;
   c->batch_max_seeds = max_windows * per_window;
-  c->batch_max_tiles = max_windows * ((per_window + kTile - 1) / kTile);
+  c->batch_scan = *sp;
+  if (c->batch_scan.block_steps == 0) c->batch_scan.block_steps = 8;
+  const int tile = scan_tile(c, &c->batch_scan);
+  c->batch_max_tiles = max_windows * ((per_window + tile - 1) / tile);
   if (c->batch_max_tiles > (int64_t(1) << 31) || c->batch_max_seeds > (int64_t(1) << 40)) {
     c->err = "batch: capacity too large; lower max_seeds_window or max_cand";
     return RKN_E_CAPACITY;
@@ -197,7 +200,7 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
     hipLaunchKernelGGL(batch_expand_kernel, dim3(1), dim3(256), 0, c->stream, c->hough_slots.as<WinSlot>(),
                        c->hough_nsel.as<int32_t>(), ne, ev_nw, ev_nt, ev_ns, c->b_windows.as<WindowDev>(),
                        c->b_tiles.as<Tile>(), c->b_ev_tiles.as<int32_t>(), c->b_ev_seed.as<long long>(),
-                       c->b_counts.as<int32_t>());
+                       c->b_counts.as<int32_t>(), tile);
     eq = hipGetLastError();
   }
   e = hipStreamEndCapture(c->stream, &c->g_hough);

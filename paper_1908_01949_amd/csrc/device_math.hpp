@@ -49,20 +49,49 @@ __device__ __forceinline__ R clampv(R v, R lo, R hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-// Bilinear (r, z) interpolation clamped to the grid edge; B_x,y = B_r (x, y)/r.
+// Square root and reciprocal: the hardware instructions (about 1 ulp) in FP32, the
+// correctly rounded ones in FP64.
 template <typename R>
-__device__ __forceinline__ void field_rz(const FieldDev& f, R x, R y, R z, R& bx, R& by, R& bz) {
-  const R r = sqrt(x * x + y * y);
-  R u = (r - (R)f.r0) * (R)f.inv_dr;
-  R v = (z - (R)f.z0) * (R)f.inv_dz;
-  u = clampv(u, (R)0, (R)(f.nr - 1));
-  v = clampv(v, (R)0, (R)(f.nz - 1));
-  int i = (int)floor(u), j = (int)floor(v);
-  i = i > f.nr - 2 ? f.nr - 2 : i;
-  j = j > f.nz - 2 ? f.nz - 2 : j;
-  const R a = clampv(u - (R)i, (R)0, (R)1);
-  const R b = clampv(v - (R)j, (R)0, (R)1);
-  const float2* row0 = f.nodes + (size_t)j * f.nr + i;
+__device__ __forceinline__ R fsqrt(R x) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_amdgcn_sqrtf(x);
+  } else {
+    return sqrt(x);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R frcp(R x) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_amdgcn_rcpf(x);
+  } else {
+    return (R)1 / x;
+  }
+}
+
+// Bilinear (r, z) interpolation clamped to the grid edge; B_x,y = B_r (x, y)/r.
+// `nodes` is the map in LDS (staged by the caller) or in global memory. The cell
+// index is truncated from the clamped coordinate, which equals the floor there.
+template <typename R>
+__device__ __forceinline__ void field_rz(const FieldDev& f, const float2* nodes, R x, R y, R z, R& bx, R& by,
+                                         R& bz) {
+  const R r2 = x * x + y * y;
+  R r, inv_r;
+  if constexpr (sizeof(R) == 4) {
+    inv_r = __builtin_amdgcn_rsqf(r2 > (R)1e-30 ? r2 : (R)1e-30);   // one transcendental
+    r = r2 * inv_r;
+  } else {
+    r = sqrt(r2);
+    inv_r = r > (R)1e-9 ? (R)1 / r : (R)0;
+  }
+  const R u = clampv((r - (R)f.r0) * (R)f.inv_dr, (R)0, (R)(f.nr - 1));
+  const R v = clampv((z - (R)f.z0) * (R)f.inv_dz, (R)0, (R)(f.nz - 1));
+  const int iu = (int)u, jv = (int)v;
+  const int i = iu < f.nr - 2 ? iu : f.nr - 2;
+  const int j = jv < f.nz - 2 ? jv : f.nz - 2;
+  const R a = u - (R)i;
+  const R b = v - (R)j;
+  const float2* row0 = nodes + j * f.nr + i;
   const float2* row1 = row0 + f.nr;
   const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
   const R br0 = (R)n00.x + a * ((R)n01.x - (R)n00.x);
@@ -71,14 +100,10 @@ __device__ __forceinline__ void field_rz(const FieldDev& f, R x, R y, R z, R& bx
   const R bz1 = (R)n10.y + a * ((R)n11.y - (R)n10.y);
   const R br = br0 + b * (br1 - br0);
   bz = bz0 + b * (bz1 - bz0);
-  if (r > (R)1e-9) {
-    const R s = br / r;
-    bx = s * x;
-    by = s * y;
-  } else {
-    bx = (R)0;
-    by = (R)0;
-  }
+  // on the axis x = y = 0, so B_x = B_y = 0 whatever inv_r is (finite here)
+  const R s = br * inv_r;
+  bx = s * x;
+  by = s * y;
 }
 
 // Propagation state. For FP32 the position and the direction carry Kahan
@@ -124,7 +149,7 @@ __device__ __forceinline__ void advance(State<R>& st, R dx, R dy, R dz) {
 // One RKN4 step (Nystrom formula for x'' = lam x' x B(x), three field evaluations:
 // start, middle, end). FIELD 0: uniform B_z; FIELD 1: (r, z) map.
 template <typename R, int FIELD>
-__device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, R h) {
+__device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, const float2* nodes, R h) {
   const R h2 = (R)0.5 * h, hh6 = h * h / (R)6, h6 = h / (R)6;
   if constexpr (FIELD == 0) {
     const R a = st.lam * (R)f.bz;
@@ -144,12 +169,12 @@ __device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, R h) {
   } else {
     const R l = st.lam;
     R bx, by, bz;
-    field_rz(f, st.x, st.y, st.z, bx, by, bz);
+    field_rz(f, nodes, st.x, st.y, st.z, bx, by, bz);
     const R k1x = l * (st.ty * bz - st.tz * by);
     const R k1y = l * (st.tz * bx - st.tx * bz);
     const R k1z = l * (st.tx * by - st.ty * bx);
     const R hh8 = h * h * (R)0.125;
-    field_rz(f, st.x + h2 * st.tx + hh8 * k1x, st.y + h2 * st.ty + hh8 * k1y,
+    field_rz(f, nodes, st.x + h2 * st.tx + hh8 * k1x, st.y + h2 * st.ty + hh8 * k1y,
              st.z + h2 * st.tz + hh8 * k1z, bx, by, bz);
     const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y, t2z = st.tz + h2 * k1z;
     const R k2x = l * (t2y * bz - t2z * by);
@@ -160,7 +185,7 @@ __device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, R h) {
     const R k3y = l * (t3z * bx - t3x * bz);
     const R k3z = l * (t3x * by - t3y * bx);
     const R hh2 = h * h * (R)0.5;
-    field_rz(f, st.x + h * st.tx + hh2 * k3x, st.y + h * st.ty + hh2 * k3y,
+    field_rz(f, nodes, st.x + h * st.tx + hh2 * k3x, st.y + h * st.ty + hh2 * k3y,
              st.z + h * st.tz + hh2 * k3z, bx, by, bz);
     const R t4x = st.tx + h * k3x, t4y = st.ty + h * k3y, t4z = st.tz + h * k3z;
     const R k4x = l * (t4y * bz - t4z * by);
@@ -190,11 +215,11 @@ __device__ __forceinline__ R seg_wire_d2(R p0x, R p0y, R p0z, R p1x, R p1y, R p1
   const R e = dx * rx + dy * ry + dz * rz;
   const R f = ux * rx + uy * ry + uz * rz;
   const R den = a - b * b;
-  R s = den > (R)1e-6 * a ? (b * f - e) / den : (R)0;
+  R s = den > (R)1e-6 * a ? (b * f - e) * frcp(den) : (R)0;
   s = clampv(s, (R)0, (R)1);
   const R t = b * s + f;
   const R tc = clampv(t, -L, L);
-  if (tc != t) s = a > (R)0 ? clampv((tc * b - e) / a, (R)0, (R)1) : (R)0;
+  if (tc != t) s = a > (R)0 ? clampv((tc * b - e) * frcp(a), (R)0, (R)1) : (R)0;
   const R vx = rx + s * dx - tc * ux;
   const R vy = ry + s * dy - tc * uy;
   const R vz = rz + s * dz - tc * uz;

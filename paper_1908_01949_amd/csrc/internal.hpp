@@ -37,8 +37,9 @@ struct DevBuf {
   }
 };
 
-// A tile is up to kTile consecutive seeds of one window (never straddles events).
-constexpr int kTile = 256;
+// A tile is up to scan_tile() consecutive seeds of one window (never straddles
+// events); kTile is the largest tile size of any scan configuration.
+constexpr int kTile = 512;
 struct Tile {
   int32_t window;
   int32_t event;
@@ -88,6 +89,7 @@ struct rkn_ctx {
   bool own_stream = false;
   std::string err;
   int n_cu = 0;
+  int max_lds_block = 65536;         // bytes of LDS one workgroup may use
 
   // geometry
   int n_wires = 0, n_layers = 0;
@@ -155,6 +157,9 @@ hipError_t launch_trace(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds, c
 rkn_status make_hough_dev(rkn_ctx* c, const rkn_hough_params* p, HoughDev& h);
 hipError_t ensure_hough_buffers(rkn_ctx* c, const HoughDev& h);
 hipError_t queue_hough_all(rkn_ctx* c, const HoughDev& h);
+
+// Seeds per tile (= lanes per workgroup) of the scan configuration for p.
+int scan_tile(const rkn_ctx* c, const rkn_scan_params* p);
 
 // Release the batched path's graphs, events and buffers (batch.hip).
 void batch_release(rkn_ctx* c);

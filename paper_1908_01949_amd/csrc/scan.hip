@@ -1,16 +1,18 @@
 // The seed-scan kernels for gfx950 (Yeo et al., CTD/WIT 2019, section 2.2, Eq. 1).
 //
 // Work decomposition (one MI355X):
-//   * one lane per seed; a 256-lane workgroup takes tiles of up to 256 seeds of one
-//     event from an atomic queue (persistent grid sized to the resident capacity);
+//   * one lane per seed; a workgroup of 64*WAVES lanes takes tiles of up to 64*WAVES
+//     seeds of one event from an atomic queue (persistent grid sized to the resident
+//     capacity); with a field map, the 65x129 (B_r, B_z) nodes are staged in LDS once
+//     per workgroup and shared by its 8 waves;
 //   * the event's hits are staged in LDS, ordered by layer, with a 1 mm radial
 //     table that maps a radius range to the range of hits whose layer band (widened
 //     by the largest drift + sqrt(lambda) + 1 mm) it can meet;
 //   * each lane runs B RKN steps in registers and writes the B+1 points to an LDS
-//     column; the wave then walks the union of its lanes' hit ranges with the hit
-//     in scalar registers, tests each (lane, hit) with a sphere bound (all B chords
-//     lie within B h / 2 of the block's middle point) and appends the survivors to
-//     an LDS work list (ballot + mbcnt compaction);
+//     column; each lane then walks its own hit range (records gathered from LDS),
+//     tests each hit with a sphere bound (all B chords lie within B h / 2 of the
+//     block's middle point) and the wave appends the survivors to an LDS work list
+//     (ballot + mbcnt compaction);
 //   * the list is processed densely: every lane takes one (seed, hit) item, computes
 //     the exact chord/wire distance of the B chords and folds the minimum into the
 //     seed's running minimum (a per-workgroup slab [hit][lane] in HBM, updated with
@@ -37,6 +39,7 @@ struct ScanArgs {
   const float* ev_maxdrift;
   int n_layers;
   int hits_bytes;             // LDS bytes reserved for hit records
+  int field_bytes;            // LDS bytes reserved for the field map (0: uniform)
   const Tile* tiles;
   int64_t n_tiles;
   const int32_t* n_tiles_dev;   // if set, the tile count is read here (captured launches)
@@ -141,7 +144,7 @@ __device__ __forceinline__ R load_coherent(const R* p) {
 }
 
 // Dense pass over a wave's work list: item = (lane << 16) | hit.
-template <typename R, int B>
+template <typename R, int B, int TILE>
 __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, const R* pts,
                                             const HitRec<R>* s_hits, R* slab, int wave, int lane,
                                             int nb) {
@@ -166,23 +169,25 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
         pz = qz;
       }
     }
-    atomic_min_nonneg(slab + (size_t)hh * kTile + wave * 64 + s, dmin);
+    atomic_min_nonneg(slab + (size_t)hh * TILE + wave * 64 + s, dmin);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R, int FIELD, int B>
-__global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
+template <typename R, int FIELD, int B, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
+  constexpr int TILE = 64 * WAVES;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  HitRec<R>* s_hits = reinterpret_cast<HitRec<R>*>(smem);
-  uint32_t* s_tab = reinterpret_cast<uint32_t*>(smem + a.hits_bytes);
-  R* s_pts = reinterpret_cast<R*>(smem + a.hits_bytes + kTabBins * 4);
-  uint32_t* s_items = reinterpret_cast<uint32_t*>(s_pts + 4 * (B + 1) * 3 * 64);
+  float2* s_field = reinterpret_cast<float2*>(smem);
+  HitRec<R>* s_hits = reinterpret_cast<HitRec<R>*>(smem + a.field_bytes);
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(smem + a.field_bytes + a.hits_bytes);
+  R* s_pts = reinterpret_cast<R*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 4);
+  uint32_t* s_items = reinterpret_cast<uint32_t*>(s_pts + WAVES * (B + 1) * 3 * 64);
   __shared__ int s_tile;
-  __shared__ double s_red_e[4];
-  __shared__ long long s_red_i[4];
+  __shared__ double s_red_e[WAVES];
+  __shared__ long long s_red_i[WAVES];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_tiles = a.n_tiles_dev ? (int64_t)*a.n_tiles_dev : a.n_tiles;
@@ -192,6 +197,12 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
   const R h = (R)a.h;
   const double lam = a.lambda;
   int cur_event = -1;
+  const float2* nodes = nullptr;
+  if constexpr (FIELD == 1) {
+    const int nn = a.field.nr * a.field.nz;
+    for (int i = tid; i < nn; i += TILE) s_field[i] = a.field.nodes[i];
+    nodes = s_field;   // made visible by the first tile's barrier
+  }
 
   for (;;) {
     if (tid == 0) s_tile = atomicAdd(a.tile_counter, 1);
@@ -205,10 +216,10 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
     const HitRec<R>* ghits = hits_of<R>(a) + hbase;
 
     if (ev != cur_event) {
-      for (int i = tid; i < nh; i += 256) s_hits[i] = ghits[i];
+      for (int i = tid; i < nh; i += TILE) s_hits[i] = ghits[i];
       const float D = a.ev_maxdrift[ev] + (float)sqrt(lam) + kBandMargin;
       const int32_t* loff = a.layer_off + (size_t)ev * (a.n_layers + 1);
-      for (int b = tid; b < kTabBins; b += 256) {
+      for (int b = tid; b < kTabBins; b += TILE) {
         const float lo_r = (float)b, hi_r = b == kTabBins - 1 ? INFINITY : (float)(b + 1);
         int l0 = 0;
         while (l0 < a.n_layers && a.layer_r[l0].y + D < lo_r) ++l0;
@@ -266,7 +277,7 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
       st.cx = st.cy = st.cz = (R)0;
       st.ctx = st.cty = st.ctz = (R)0;
     }
-    for (int i = 0; i < nh; ++i) slab[(size_t)i * kTile + tid] = (R)INFINITY;
+    for (int i = 0; i < nh; ++i) slab[(size_t)i * TILE + tid] = (R)INFINITY;
     __threadfence_block();
     __syncthreads();
 
@@ -282,7 +293,7 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
       R cx = st.x, cy = st.y, cz = st.z;
 #pragma unroll
       for (int j = 1; j <= B; ++j) {
-        if (j <= nb) rkn_step<R, FIELD>(st, a.field, h);
+        if (j <= nb) rkn_step<R, FIELD>(st, a.field, nodes, h);
         pts[(j * 3 + 0) * 64 + lane] = st.x;
         pts[(j * 3 + 1) * 64 + lane] = st.y;
         pts[(j * 3 + 2) * 64 + lane] = st.z;
@@ -296,33 +307,36 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
         }
       }
       // radial range of the block's chords (a chord point is within h/2 of an endpoint)
-      const float rmin = fmaxf((float)sqrt(r2min) - 0.5f * (float)a.h, 0.0f);
-      const float rmax = (float)sqrt(r2max);
+      const float rmin = fmaxf((float)fsqrt(r2min) - 0.5f * (float)a.h, 0.0f);
+      const float rmax = (float)fsqrt(r2max);
       // clamp in float first: fminf/fmaxf map NaN to the bound, so the index is in range
       const int b_lo = (int)fminf(fmaxf(rmin, 0.0f), (float)(kTabBins - 1));
       const int b_hi = (int)fminf(fmaxf(rmax, 0.0f), (float)(kTabBins - 1));
-      const int hlo = valid ? (int)(s_tab[b_lo] & 0xffffu) : 0x7fffffff;
-      const int hhi = valid ? (int)(s_tab[b_hi] >> 16) : 0;
-      const int H_lo = wave_min_i32(hlo), H_hi = wave_max_i32(hhi);
+      // each lane walks its own band range; hit records are gathered from LDS
+      const int my_lo = (int)(s_tab[b_lo] & 0xffffu);
+      const int my_n = valid ? max((int)(s_tab[b_hi] >> 16) - my_lo, 0) : 0;
+      const int kmax = wave_max_i32(my_n);
       int n_items = 0;
-      for (int hh = H_lo; hh < H_hi; ++hh) {
-        const HitRec<R> w = load_hit_uniform(ghits, hh);
+      for (int k = 0; k < kmax; ++k) {
+        const bool act = k < my_n;
+        const int hh = act ? my_lo + k : 0;
+        const HitRec<R> w = s_hits[hh];
         const R rx = cx - w.mx, ry = cy - w.my, rz = cz - w.mz;
         const R tt = rx * w.ux + ry * w.uy + rz * w.uz;
         const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
         const R thr = Kcull + w.drift;
-        const bool pass = valid && (d2 <= thr * thr);
+        const bool pass = act && (d2 <= thr * thr);
         const uint64_t m = __ballot(pass);
         if (m) {
           if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
           n_items += (int)__popcll(m);
           if (n_items > kCap - 64) {
-            flush_items<R, B>(items, n_items, pts, s_hits, slab, wave, lane, nb);
+            flush_items<R, B, TILE>(items, n_items, pts, s_hits, slab, wave, lane, nb);
             n_items = 0;
           }
         }
       }
-      if (n_items) flush_items<R, B>(items, n_items, pts, s_hits, slab, wave, lane, nb);
+      if (n_items) flush_items<R, B, TILE>(items, n_items, pts, s_hits, slab, wave, lane, nb);
     }
     __threadfence();
 
@@ -331,7 +345,7 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
     int cnt = 0;
     if (valid) {
       for (int i = 0; i < nh; ++i) {
-        const R m2 = load_coherent(slab + (size_t)i * kTile + tid);
+        const R m2 = load_coherent(slab + (size_t)i * TILE + tid);
         const double r = sqrt((double)m2) - (double)s_hits[i].drift;
         const double tq = r * r;
         if (tq < lam) {
@@ -366,7 +380,7 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-      for (int k = 1; k < 4; ++k)
+      for (int k = 1; k < WAVES; ++k)
         if (s_red_e[k] < be || (s_red_e[k] == be && s_red_i[k] < idx)) {
           be = s_red_e[k];
           idx = s_red_i[k];
@@ -415,47 +429,53 @@ event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restr
   }
 }
 
-template <typename R, int FIELD, int B>
+template <typename R, int FIELD, int B, int WAVES>
 static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only) {
+  constexpr int TILE = 64 * WAVES;
   const int hits_bytes = ((c->max_hits_event * (int)sizeof(HitRec<R>)) + 255) & ~255;
+  const int field_bytes = FIELD == 1 ? ((c->nr * c->nz * (int)sizeof(float2)) + 255) & ~255 : 0;
   a.hits_bytes = hits_bytes;
-  const size_t smem = (size_t)hits_bytes + kTabBins * 4 + 4 * (B + 1) * 3 * 64 * sizeof(R) +
-                      4 * kCap * sizeof(uint32_t);
-  if (smem > 65536) return hipErrorInvalidConfiguration;
-  auto kern = scan_kernel<R, FIELD, B>;
+  a.field_bytes = field_bytes;
+  const size_t smem = (size_t)field_bytes + hits_bytes + kTabBins * 4 + WAVES * (B + 1) * 3 * 64 * sizeof(R) +
+                      WAVES * kCap * sizeof(uint32_t);
+  if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
+  auto kern = scan_kernel<R, FIELD, B, WAVES>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, smem);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TILE, smem);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   int64_t grid = (int64_t)per_cu * c->n_cu;
   if (grid > max_tiles) grid = max_tiles;
   if (grid < 1) grid = 1;
-  a.slab_stride = (int64_t)(c->max_hits_event > 0 ? c->max_hits_event : 1) * kTile;
+  a.slab_stride = (int64_t)(c->max_hits_event > 0 ? c->max_hits_event : 1) * TILE;
   e = c->mscratch.ensure((size_t)grid * a.slab_stride * sizeof(R));
   if (e != hipSuccess) return e;
   a.mscratch = c->mscratch.p;
   if (alloc_only) return hipSuccess;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, c->stream, a.tile_counter);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), smem, c->stream, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TILE), smem, c->stream, a);
   return hipGetLastError();
 }
 
-template <typename R, int FIELD, int B>
-static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t n_tiles) {
-  return launch_scan_t<R, FIELD, B>(c, a, n_tiles, false);
+// Kernel configuration per (precision, field): the field map path uses 8 waves per
+// workgroup so that the map staged in LDS serves 512 seeds.
+int scan_tile(const rkn_ctx* c, const rkn_scan_params* p) {
+  return (p->precision == 32 && c->field_kind == 1) ? 512 : 256;
 }
 
 static hipError_t dispatch_scan(rkn_ctx* c, const rkn_scan_params* p, ScanArgs& a, int64_t max_tiles,
                                 bool alloc_only) {
   const int B = p->block_steps;
   if (p->precision == 64)
-    return c->field_kind == 0 ? launch_scan_t<double, 0, 4>(c, a, max_tiles, alloc_only)
-                              : launch_scan_t<double, 1, 4>(c, a, max_tiles, alloc_only);
+    return c->field_kind == 0 ? launch_scan_t<double, 0, 4, 4>(c, a, max_tiles, alloc_only)
+                              : launch_scan_t<double, 1, 4, 4>(c, a, max_tiles, alloc_only);
   if (c->field_kind == 0)
-    return B == 4 ? launch_scan_t<float, 0, 4>(c, a, max_tiles, alloc_only)
-                  : launch_scan_t<float, 0, 8>(c, a, max_tiles, alloc_only);
-  return B == 4 ? launch_scan_t<float, 1, 4>(c, a, max_tiles, alloc_only)
-                : launch_scan_t<float, 1, 8>(c, a, max_tiles, alloc_only);
+    return B == 4 ? launch_scan_t<float, 0, 4, 4>(c, a, max_tiles, alloc_only)
+                  : launch_scan_t<float, 0, 8, 4>(c, a, max_tiles, alloc_only);
+  return B == 4 ? launch_scan_t<float, 1, 4, 8>(c, a, max_tiles, alloc_only)
+                : launch_scan_t<float, 1, 8, 8>(c, a, max_tiles, alloc_only);
 }
 
 FieldDev field_dev(const rkn_ctx* c) {
@@ -568,7 +588,7 @@ trace_kernel(FieldDev f, double R0, double charge, double hstep, int64_t n_seeds
   for (int k = 0; k < n_sel; ++k) {
     const int target = steps[k];
     while (n < target) {
-      rkn_step<R, FIELD>(st, f, h);
+      rkn_step<R, FIELD>(st, f, f.nodes, h);
       ++n;
     }
     o[6 * k + 0] = (double)st.x;
