@@ -82,6 +82,136 @@ def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_ste
         dict(cull_per_step=cull / ss, pairs_per_step=pairs / ss, sample_max_rel_score_err=rel)
 
 
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rtol=1e-3,
+               scale=(1.0, 100.0, 100.0, 100.0, 100.0)):
+    """Refinement of the k best seeds per event of the batch just scanned, two ways:
+    (a) Gauss-Newton with the adjoint sweep (gn_iters iterations), and (b) the paper's
+    coarse-to-fine rescans (section 2.2): 6^5 grids around the current k best seeds
+    whose half-width is the previous grid step, the k best of each round kept, until
+    the best seed's Phi on the inlier set of the event's best Gauss-Newton seed is
+    within (1 + rtol) of that seed's Phi, or max_rounds. Both legs include the shared
+    coarse scan time; the Phi checks of (b) are not timed."""
+    import torch
+    ne = n_events
+    (idx, sc, s5), t_topk = _sync_time(lambda: rk.rkn_batch_topk(ctx.ctx, k, n_events=ne))
+    windows, _, _, ev_seed = rk.rkn_batch_results(ctx.ctx, ne, want_scores=False)
+    sizes = np.prod(windows["count"].astype(np.int64), axis=1)
+    wbase = np.concatenate([[0], np.cumsum(sizes)])
+    ok = idx >= 0
+    ev_of = np.repeat(np.arange(ne, dtype=np.int32), k).reshape(ne, k)
+    seed_event = ev_of[ok]
+    seeds = s5[ok]
+    # (a) Gauss-Newton
+    p = rk.make_scan_params(n_steps=sp.n_steps, precision=32, lambda_mm2=sp.lambda_mm2)
+    nsd = seed_event.size
+
+    def gn():
+        rk.rkn_refine_setup(ctx.ctx, p, seed_event, seeds, 64)
+        out = np.zeros((nsd, 5)); phi = np.zeros((nsd, gn_iters + 1))
+        rk.rkn_gn_refine(ctx.ctx, gn_iters, np.asarray(scale), out, phi)
+        return out, phi
+    (gn_seeds, gn_phi), t_gn = _sync_time(gn)
+    phi_fin = gn_phi[:, -1]
+    best_slot = np.full(ne, -1)
+    for e in range(ne):
+        sl = np.nonzero(seed_event == e)[0]
+        if sl.size:
+            best_slot[e] = sl[np.argmin(phi_fin[sl])]
+    has = best_slot >= 0
+    phi_gn = np.where(has, phi_fin[np.maximum(best_slot, 0)], np.nan)
+    log(f"refine: {nsd} seeds, top-{k} {t_topk * 1e3:.1f} ms, GN {gn_iters} it {t_gn * 1e3:.1f} ms, "
+        f"Phi {np.nanmean(gn_phi[:, 0]):.3g} -> {np.nanmean(phi_fin):.3g}")
+
+    def phi_on_gn_set(cand):
+        """Phi of cand[e] on the inlier set of event e's best GN seed (not timed)."""
+        trial = gn_seeds.copy()
+        sel = has & np.all(np.isfinite(cand), axis=1)
+        trial[best_slot[sel]] = cand[sel]
+        ph = np.zeros(nsd)
+        rk.rkn_residuals_fwd(ctx.ctx, trial, None, ph)
+        out = np.full(ne, np.inf)
+        out[sel] = ph[best_slot[sel]]
+        return out
+
+    # (b) rescans: the previous grid step of each coarse pick is its window's step
+    kw = np.searchsorted(wbase, np.where(ok, idx, 0), side="right") - 1
+    cnt = windows["count"][kw].astype(np.float64)
+    step = np.where(cnt > 1, 2.0 * windows["half_width"][kw] / np.maximum(cnt - 1, 1), 0.0)
+    cur = s5.copy()
+    cur_ok = ok.copy()
+    active = has.copy()
+    rounds = np.zeros(ne, np.int64)
+    reached = np.zeros(ne, bool)
+    t_rounds = 0.0
+    seeds_scanned = 0
+    for r in range(max_rounds):
+        ev_act = np.nonzero(active)[0]
+        if ev_act.size == 0:
+            break
+        rows = [(e, j) for e in ev_act for j in range(k) if cur_ok[e, j]]
+        w = np.zeros(len(rows), synth.WINDOW_DTYPE)
+        ee = np.array([e for e, _ in rows]); jj = np.array([j for _, j in rows])
+        w["event"] = ee
+        w["candidate"] = jj
+        w["center"] = cur[ee, jj]
+        w["half_width"] = step[ee, jj]
+        w["count"] = 6
+        (nidx, nsc, ns5), dt = _sync_time(lambda: rk.rkn_scan_windows_topk(ctx.ctx, sp, w, k, n_events=ne))
+        t_rounds += dt
+        seeds_scanned += len(rows) * 6 ** 5
+        # the k best of this round, each with the step of the grid it came from
+        widx = np.zeros(ne, np.int64)
+        wsz = 6 ** 5
+        first_row = np.full(ne, -1)
+        for i, e in enumerate(ee):
+            if first_row[e] < 0:
+                first_row[e] = i
+        gb = np.zeros(ne, np.int64)
+        acc = 0
+        for e in range(ne):
+            gb[e] = acc
+            acc += int((ee == e).sum()) * wsz
+        new_step = np.zeros_like(step)
+        for e in ev_act:
+            for j in range(k):
+                g = nidx[e, j]
+                if g < 0:
+                    cur_ok[e, j] = False
+                    continue
+                row = first_row[e] + (g - gb[e]) // wsz
+                new_step[e, j] = 2.0 * w["half_width"][row] / 5.0
+                cur[e, j] = ns5[e, j]
+                cur_ok[e, j] = True
+        step = np.where(active[:, None], new_step, step)
+        rounds[ev_act] += 1
+        ph = phi_on_gn_set(ns5[:, 0, :])
+        done = active & (ph <= (1.0 + rtol) * phi_gn)
+        reached |= done
+        active &= ~done
+        log(f"rescan round {r + 1}: {len(rows)} windows, {dt * 1e3:.1f} ms, {int(done.sum())} events reached, "
+            f"{int(active.sum())} left")
+    t_a = t_coarse + t_topk + t_gn
+    t_b = t_coarse + t_topk + t_rounds
+    return dict(
+        seeds=int(nsd), k=k, gn_iters=gn_iters, ckpt_every=64,
+        ms_coarse=round(t_coarse * 1e3, 2), ms_topk=round(t_topk * 1e3, 2), ms_gn=round(t_gn * 1e3, 2),
+        ms_rescans=round(t_rounds * 1e3, 2), rescan_seeds=int(seeds_scanned),
+        events_per_s_gn=ne / t_a, events_per_s_rescan=ne / t_b, speedup=t_b / t_a,
+        rescan_rounds_mean=float(rounds[has].mean()) if has.any() else 0.0,
+        events_reached=int(reached.sum()), events_with_seeds=int(has.sum()),
+        phi_gn_mean=float(np.nanmean(phi_gn)), phi_start_mean=float(np.nanmean(gn_phi[:, 0])),
+        rule=f"rescans stop per event when Phi <= (1+{rtol:g}) Phi_GN on the GN inlier set, <= {max_rounds} rounds")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +221,7 @@ def main():
     ap.add_argument("--rkn-steps", type=int, default=6000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-refine", action="store_true", help="skip the refinement comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -175,6 +306,9 @@ def main():
     }
     if work is not None:
         out["sample_max_rel_score_err"] = work["sample_max_rel_score_err"]
+    if not args.no_refine:
+        out["refine"] = refine_leg(ctx, sp, ne, dt / args.steps)
+        log(f"refine: {out['refine']}")
     ctx.close()
     print(json.dumps(out))
 

@@ -46,6 +46,7 @@ typedef int32_t rkn_status;
 
 #define RKN_MAX_HITS_PER_EVENT 512
 #define RKN_MAX_LAYERS 64
+#define RKN_TOPK_MAX 16            /* largest k of the top-k selections */
 
 typedef struct rkn_ctx rkn_ctx;
 
@@ -173,6 +174,18 @@ rkn_status rkn_scan_windows(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_wi
                             const rkn_window *w, double *score, int32_t *n_in,
                             int64_t *best_index, double *best_score);
 
+/* The scan of rkn_scan_windows followed by the choice of the k (1..RKN_TOPK_MAX)
+ * lowest-score seeds of every event, on the device: the step of the coarse-to-fine
+ * refinement that keeps the best seeds of a scan before finer seed sets are built
+ * around them (section 2.2). Per event, ordered by (score, global seed index):
+ * index [n_events][k] (global seed index as in rkn_scan_windows, -1 when the event
+ * has fewer than k seeds), score [n_events][k] (+inf padding) and, unless NULL,
+ * seeds5 [n_events][k][5] (the decoded seeds, NaN padding). NaN scores are never
+ * chosen. Outputs follow p->ptr_flags; the per-seed scores stay on the device. */
+rkn_status rkn_scan_windows_topk(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_windows,
+                                 const rkn_window *w, int32_t k, int64_t *index, double *score,
+                                 double *seeds5);
+
 /* Same score for an explicit seed list (SoA, host arrays, FP64). best_index is the
  * position in the list. */
 rkn_status rkn_scan_seeds(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds,
@@ -188,8 +201,8 @@ rkn_status rkn_trace(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, co
 
 /* ---- Batched scan of every uploaded event ---------------------------------------
  * The Hough stage, the expansion of its windows into seed tiles, one persistent
- * scan launch over all tiles (an atomic work queue of up to 256 seeds of one
- * window each) and the per-event argmin, captured once as HIP graphs on the
+ * scan launch over all tiles (an atomic work queue of tiles of up to 512 seeds of
+ * one window each) and the per-event argmin, captured once as HIP graphs on the
  * context's stream. Re-plan after uploading new hits or geometry. */
 
 /* Validate the parameters, size every buffer for the worst case
@@ -203,6 +216,13 @@ rkn_status rkn_batch_plan(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_sc
  * rkn_scan_windows. Either may be NULL. */
 rkn_status rkn_batch_launch(rkn_ctx *ctx, int64_t *best_index, double *best_score);
 
+/* After a launch: the k (1..RKN_TOPK_MAX) lowest-score seeds of every event of the
+ * batch, chosen on the device, with the same outputs and order as
+ * rkn_scan_windows_topk (global seed indices of the batch). Outputs follow the
+ * planned sp->ptr_flags. This is how the best seeds of a batch reach the
+ * refinement below. */
+rkn_status rkn_batch_topk(rkn_ctx *ctx, int32_t k, int64_t *index, double *score, double *seeds5);
+
 /* After a launch (waits for it): number of windows and seeds of the batch, and the
  * HIP-event time of the Hough+expansion graph and of the scan graph, in ms. */
 rkn_status rkn_batch_info(rkn_ctx *ctx, int32_t *n_windows, int64_t *n_seeds, float *ms_hough,
@@ -213,6 +233,44 @@ rkn_status rkn_batch_info(rkn_ctx *ctx, int32_t *n_windows, int64_t *n_seeds, fl
  * [n_events+1]. Any output may be NULL; RKN_E_CAPACITY if a capacity is short. */
 rkn_status rkn_batch_results(rkn_ctx *ctx, int32_t max_windows, rkn_window *windows, int32_t *n_windows,
                              int64_t max_seeds, double *score, int32_t *n_in, int64_t *ev_seed_off);
+
+/* ---- Differentiated refinement of seeds --------------------------------------------
+ * The paper refines the best seeds by rescanning finer grids (section 2.2); this is
+ * the derivative-based alternative. Per seed the objective is
+ *   Phi = sum over the inlier set S of r_i^2,  r_i = D_i - d_i,
+ * with S fixed by the classification rule (D - d)^2 < lambda at the seed given to
+ * rkn_refine_setup. Derivatives are those of the discrete RKN map; D_i's gradient is
+ * that of its minimising chord at the minimising parameters. Propagation is FP32
+ * with a checkpoint of the full state every ckpt_every steps; the adjoint sweep
+ * recomputes each segment from its checkpoint and accumulates in FP64. Seeds must be
+ * grouped by event (non-decreasing seed_event); every array below is in that seed
+ * order. Outputs follow p->ptr_flags (host or device pointers). */
+
+/* Upload n_seeds seeds ([n][5] host, FP64) and fix their inlier sets. p->precision
+ * must be 32; ckpt_every a multiple of 8 in [8, 4096]. */
+rkn_status rkn_refine_setup(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, const int32_t *seed_event,
+                            const double *seeds5, int32_t ckpt_every);
+
+/* Forward pass at seeds5 ([n][5]; NULL keeps the current seeds): resid [n][H]
+ * (H = the largest hit count of an uploaded event; per row the event's hits in
+ * upload order, NaN for hits outside the inlier set and for unused columns) and
+ * phi [n]. Records the checkpoints used by rkn_adjoint_bwd. Either output may be NULL. */
+rkn_status rkn_residuals_fwd(rkn_ctx *ctx, const double *seeds5, float *resid, double *phi);
+
+/* Adjoint of the last forward pass. d_resid [n][H]: upstream gradient dF/dr (entries
+ * of non-inliers ignored), or NULL for F = Phi (dF/dr = 2 r). d_seed [n][5] =
+ * dF/d(theta, z0, px, py, pz); JtJ [n][5][5] = J^T J and Jtr [n][5] = J^T r of the
+ * inlier residuals (J^T r is grad(Phi)/2, defined for d_resid == NULL). Any output may
+ * be NULL; JtJ adds the second-order sweep. */
+rkn_status rkn_adjoint_bwd(rkn_ctx *ctx, const float *d_resid, double *d_seed, double *JtJ, double *Jtr);
+
+/* Gauss-Newton from the setup seeds: iters iterations of the normal equations
+ * (J^T J) delta = -J^T r solved in FP64 by Cholesky in the scaled variables
+ * D delta (D = diag(scale[5]); 1e-12 trace added if not positive definite), a step
+ * taken at the first alpha in 1, 1/2, ..., 1/32 that lowers Phi (else the seed
+ * stays). seeds_out [n][5]; phi [n][iters+1] (Phi before each iteration and after
+ * the last). */
+rkn_status rkn_gn_refine(rkn_ctx *ctx, int32_t iters, const double *scale, double *seeds_out, double *phi);
 
 #ifdef __cplusplus
 }

@@ -127,12 +127,14 @@ void rkn_destroy(rkn_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   rkn::batch_release(c);
+  c->refine_release();
   DevBuf* bufs[] = {&c->wire32, &c->wire64, &c->wire_layer, &c->layer_r, &c->field_nodes, &c->ev_off,
                     &c->hits32, &c->hits64, &c->layer_off, &c->ev_maxdrift, &c->windows, &c->tiles,
                     &c->ev_tiles, &c->parts, &c->counter, &c->mscratch, &c->out_score, &c->out_nin,
                     &c->out_best_i, &c->out_best_e, &c->trace_buf, &c->seeds_buf, &c->perm_buf,
                     &c->wire_wx, &c->wire_wy, &c->hits_wire, &c->hough_acc, &c->hough_max,
-                    &c->hough_cand_n, &c->hough_cand, &c->hough_slots, &c->hough_nsel};
+                    &c->hough_cand_n, &c->hough_cand, &c->hough_slots, &c->hough_nsel, &c->hits_orig,
+                    &c->sel_seg, &c->sel_win, &c->sel_idx, &c->sel_sc, &c->sel_seed};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->extra) b.release();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -202,6 +204,7 @@ rkn_status rkn_upload_geometry(rkn_ctx* c, int32_t n_wires, const double* mx, co
   c->h_ev_off.clear();       // hits refer to the old wire table
   c->n_events = 0;
   rkn::batch_release(c);
+  c->refine_release();
   return RKN_OK;
 }
 
@@ -269,6 +272,7 @@ rkn_status rkn_upload_hits(rkn_ctx* c, int32_t n_events, const int32_t* ev_off, 
   }
   RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
   rkn::batch_release(c);   // a planned batch refers to the previous events
+  c->refine_release();     // so do refinement seeds and their inlier sets
   DevBuf d_drift;
   DevBuf& d_wid = c->hits_wire;
   hipError_t e = upload(c->ev_off, ev_off, (size_t)n_events + 1, c->stream);
@@ -278,6 +282,7 @@ rkn_status rkn_upload_hits(rkn_ctx* c, int32_t n_events, const int32_t* ev_off, 
   if (e == hipSuccess) e = c->hits64.ensure(sizeof(rkn::HitRec<double>) * (size_t)std::max<int64_t>(H, 1));
   if (e == hipSuccess) e = c->layer_off.ensure(sizeof(int32_t) * (size_t)n_events * (c->n_layers + 1));
   if (e == hipSuccess) e = c->ev_maxdrift.ensure(sizeof(float) * (size_t)n_events);
+  if (e == hipSuccess) e = c->hits_orig.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(H, 1));
   if (e == hipSuccess) {
     c->n_events = n_events;
     e = rkn::launch_prep_hits(c, d_wid.as<int32_t>(), d_drift.as<float>());
@@ -354,19 +359,20 @@ static rkn_status run_scan(rkn_ctx* c, const rkn_scan_params* p, std::vector<rkn
   return RKN_OK;
 }
 
-rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
-                            double* score, int32_t* n_in, int64_t* best_index, double* best_score) {
-  if (!c) return RKN_E_ARG;
-  rkn_status st = check_scan_params(c, p);
-  if (st != RKN_OK) return st;
-  if ((st = check_state(c)) != RKN_OK) return st;
+// Windows -> device windows, tiles and per-event tile, seed and window offsets
+// (windows must be ordered by event; an event's seeds are contiguous).
+static rkn_status prepare_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
+                                  std::vector<rkn::WindowDev>& wins, std::vector<rkn::Tile>& tiles,
+                                  std::vector<int32_t>& ev_tiles, int64_t& total, std::vector<long long>* ev_seed,
+                                  std::vector<int32_t>* ev_win) {
   if (n_windows < 0 || (n_windows > 0 && !w)) return arg_err(c, "bad window array");
-  if (!best_index || !best_score) return arg_err(c, "best_index/best_score must not be NULL");
-  std::vector<rkn::WindowDev> wins(std::max(n_windows, 1));
-  std::vector<rkn::Tile> tiles;
-  std::vector<int32_t> ev_tiles(c->n_events + 1, 0);
+  wins.assign(std::max(n_windows, 1), rkn::WindowDev{});
+  tiles.clear();
+  ev_tiles.assign(c->n_events + 1, 0);
+  if (ev_seed) ev_seed->assign(c->n_events + 1, 0);
+  if (ev_win) ev_win->assign(c->n_events + 1, 0);
   const int T = rkn::scan_tile(c, p);
-  int64_t total = 0;
+  total = 0;
   int last_ev = -1;
   for (int k = 0; k < n_windows; ++k) {
     const rkn_window& x = w[k];
@@ -380,7 +386,11 @@ rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_wind
       size *= x.count[d];
       if (size > (int64_t(1) << 40)) return arg_err(c, "window too large");
     }
-    for (int e = last_ev + 1; e <= x.event; ++e) ev_tiles[e] = (int32_t)tiles.size();
+    for (int e = last_ev + 1; e <= x.event; ++e) {
+      ev_tiles[e] = (int32_t)tiles.size();
+      if (ev_seed) (*ev_seed)[e] = total;
+      if (ev_win) (*ev_win)[e] = k;
+    }
     last_ev = x.event;
     rkn::WindowDev& d = wins[k];
     for (int j = 0; j < 5; ++j) {
@@ -400,9 +410,89 @@ rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_wind
     }
     total += size;
   }
-  for (int e = last_ev + 1; e <= c->n_events; ++e) ev_tiles[e] = (int32_t)tiles.size();
+  for (int e = last_ev + 1; e <= c->n_events; ++e) {
+    ev_tiles[e] = (int32_t)tiles.size();
+    if (ev_seed) (*ev_seed)[e] = total;
+    if (ev_win) (*ev_win)[e] = n_windows;
+  }
+  return RKN_OK;
+}
+
+rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
+                            double* score, int32_t* n_in, int64_t* best_index, double* best_score) {
+  if (!c) return RKN_E_ARG;
+  rkn_status st = check_scan_params(c, p);
+  if (st != RKN_OK) return st;
+  if ((st = check_state(c)) != RKN_OK) return st;
+  if (!best_index || !best_score) return arg_err(c, "best_index/best_score must not be NULL");
+  std::vector<rkn::WindowDev> wins;
+  std::vector<rkn::Tile> tiles;
+  std::vector<int32_t> ev_tiles;
+  int64_t total = 0;
+  if ((st = prepare_windows(c, p, n_windows, w, wins, tiles, ev_tiles, total, nullptr, nullptr)) != RKN_OK)
+    return st;
   RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
   return run_scan(c, p, wins, tiles, ev_tiles, total, score, n_in, best_index, best_score);
+}
+
+rkn_status rkn_scan_windows_topk(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
+                                 int32_t k, int64_t* index, double* score, double* seeds5) {
+  if (!c) return RKN_E_ARG;
+  rkn_status st = check_scan_params(c, p);
+  if (st != RKN_OK) return st;
+  if ((st = check_state(c)) != RKN_OK) return st;
+  if (k < 1 || k > RKN_TOPK_MAX || !index || !score) return arg_err(c, "topk: k in [1, 16] and index/score outputs");
+  std::vector<rkn::WindowDev> wins;
+  std::vector<rkn::Tile> tiles;
+  std::vector<int32_t> ev_tiles, ev_win;
+  std::vector<long long> ev_seed;
+  int64_t total = 0;
+  if ((st = prepare_windows(c, p, n_windows, w, wins, tiles, ev_tiles, total, &ev_seed, &ev_win)) != RKN_OK)
+    return st;
+  RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const bool dev = (p->ptr_flags & RKN_PTR_DEVICE) != 0;
+  const size_t ne = (size_t)c->n_events;
+  RKN_HIP(upload(c->windows, wins.data(), wins.size(), c->stream), "window upload");
+  RKN_HIP(upload(c->tiles, tiles.data(), std::max<size_t>(tiles.size(), 1), c->stream), "tile upload");
+  RKN_HIP(upload(c->ev_tiles, ev_tiles.data(), ev_tiles.size(), c->stream), "tile upload");
+  RKN_HIP(upload(c->sel_seg, ev_seed.data(), ev_seed.size(), c->stream), "offset upload");
+  RKN_HIP(upload(c->sel_win, ev_win.data(), ev_win.size(), c->stream), "offset upload");
+  RKN_HIP(c->out_score.ensure(sizeof(double) * (size_t)std::max<int64_t>(total, 1)), "alloc");
+  RKN_HIP(c->out_best_i.ensure(sizeof(int64_t) * ne), "alloc");
+  RKN_HIP(c->out_best_e.ensure(sizeof(double) * ne), "alloc");
+  int64_t* d_idx = index;
+  double* d_sc = score;
+  double* d_seed = seeds5;
+  if (!dev) {
+    RKN_HIP(c->sel_idx.ensure(sizeof(int64_t) * ne * k), "alloc");
+    RKN_HIP(c->sel_sc.ensure(sizeof(double) * ne * k), "alloc");
+    RKN_HIP(c->sel_seed.ensure(sizeof(double) * ne * k * 5), "alloc");
+    d_idx = c->sel_idx.as<int64_t>();
+    d_sc = c->sel_sc.as<double>();
+    d_seed = seeds5 ? c->sel_seed.as<double>() : nullptr;
+  }
+  rkn_scan_params q = *p;
+  if (q.block_steps == 0) q.block_steps = 8;
+  hipError_t e = rkn::launch_scan(c, &q, (int64_t)tiles.size(), c->tiles.as<rkn::Tile>(),
+                                  c->windows.as<rkn::WindowDev>(), nullptr, nullptr, c->out_score.as<double>(),
+                                  nullptr, c->out_best_i.as<int64_t>(), c->out_best_e.as<double>(),
+                                  c->ev_tiles.as<int32_t>());
+  if (e == hipErrorInvalidConfiguration) {
+    c->err = "scan configuration does not fit the device (LDS per workgroup); use FP32 or fewer hits per event";
+    return RKN_E_UNSUPPORTED;
+  }
+  if (e != hipSuccess) return dev_err(c, e, "scan launch");
+  e = rkn::launch_topk(c, c->out_score.as<double>(), c->sel_seg.as<long long>(), c->windows.as<rkn::WindowDev>(),
+                       c->sel_win.as<int32_t>(), c->n_events, c->sel_win.as<int32_t>() + c->n_events, k, d_idx,
+                       d_sc, d_seed);
+  if (e != hipSuccess) return dev_err(c, e, "topk launch");
+  if (!dev) {
+    RKN_HIP(deliver(c, index, d_idx, ne * k, false), "copy topk");
+    RKN_HIP(deliver(c, score, d_sc, ne * k, false), "copy topk");
+    if (seeds5) RKN_HIP(deliver(c, seeds5, d_seed, ne * k * 5, false), "copy topk");
+    RKN_HIP(hipStreamSynchronize(c->stream), "topk");
+  }
+  return RKN_OK;
 }
 
 rkn_status rkn_scan_seeds(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds, const int32_t* seed_event,

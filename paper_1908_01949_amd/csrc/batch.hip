@@ -104,6 +104,17 @@ void drop_graphs(rkn_ctx* c) {
   c->x_hough = c->x_scan = nullptr;
   c->g_hough = c->g_scan = nullptr;
   c->batch_ready = false;
+  c->batch_launched = false;
+}
+
+// Addresses of the shared Hough buffers that the captured graph A refers to.
+void hough_ptrs(const rkn_ctx* c, void* out[6]) {
+  out[0] = c->hough_acc.p;
+  out[1] = c->hough_max.p;
+  out[2] = c->hough_cand_n.p;
+  out[3] = c->hough_cand.p;
+  out[4] = c->hough_slots.p;
+  out[5] = c->hough_nsel.p;
 }
 
 }  // namespace
@@ -117,7 +128,8 @@ void batch_release(rkn_ctx* c) {
   if (c->ev_t2) (void)hipEventDestroy(c->ev_t2);
   c->ev_t0 = c->ev_t1 = c->ev_t2 = nullptr;
   DevBuf* bufs[] = {&c->b_windows, &c->b_tiles, &c->b_ev_tiles, &c->b_counts, &c->b_ev_seed,
-                    &c->b_score, &c->b_nin, &c->b_best_i, &c->b_best_e, &c->b_ev_scratch};
+                    &c->b_score,   &c->b_nin,   &c->b_best_i,   &c->b_best_e, &c->b_ev_scratch,
+                    &c->b_slab,    &c->b_parts, &c->b_counter};
   for (DevBuf* b : bufs) b->release();
 }
 
@@ -220,6 +232,7 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
   if (e != hipSuccess) return berr(c, e, "batch capture end");
   if ((e = hipGraphInstantiate(&c->x_scan, c->g_scan, nullptr, nullptr, 0)) != hipSuccess)
     return berr(c, e, "batch instantiate");
+  hough_ptrs(c, c->b_hough_ptrs);
   c->batch_ready = true;
   return RKN_OK;
 }
@@ -230,6 +243,17 @@ rkn_status rkn_batch_launch(rkn_ctx* c, int64_t* best_index, double* best_score)
     c->err = "batch: call rkn_batch_plan first";
     return RKN_E_STATE;
   }
+  // an eager Hough call with a larger accumulator since the plan moved a buffer that
+  // the captured graph still points at (buffers only grow, so an unchanged address
+  // is still large enough)
+  void* now[6];
+  hough_ptrs(c, now);
+  for (int i = 0; i < 6; ++i)
+    if (now[i] != c->b_hough_ptrs[i]) {
+      drop_graphs(c);
+      c->err = "batch: Hough buffers were reallocated since rkn_batch_plan; plan again";
+      return RKN_E_STATE;
+    }
   hipError_t e;
   if ((e = hipSetDevice(c->device)) != hipSuccess) return berr(c, e, "hipSetDevice");
   if ((e = hipEventRecord(c->ev_t0, c->stream)) != hipSuccess) return berr(c, e, "batch event");
@@ -246,13 +270,56 @@ rkn_status rkn_batch_launch(rkn_ctx* c, int64_t* best_index, double* best_score)
       (e = hipMemcpyAsync(best_score, c->b_best_e.p, sizeof(double) * c->n_events, kind, c->stream)) != hipSuccess)
     return berr(c, e, "batch copy");
   if (!dev && (e = hipStreamSynchronize(c->stream)) != hipSuccess) return berr(c, e, "batch sync");
+  c->batch_launched = true;
+  return RKN_OK;
+}
+
+rkn_status rkn_batch_topk(rkn_ctx* c, int32_t k, int64_t* index, double* score, double* seeds5) {
+  if (!c) return RKN_E_ARG;
+  if (!c->batch_ready || !c->batch_launched) {
+    c->err = "batch: call rkn_batch_plan and rkn_batch_launch first";
+    return RKN_E_STATE;
+  }
+  if (k < 1 || k > RKN_TOPK_MAX || !index || !score) {
+    c->err = "batch topk: k in [1, 16] and index/score outputs";
+    return RKN_E_ARG;
+  }
+  hipError_t e;
+  if ((e = hipSetDevice(c->device)) != hipSuccess) return berr(c, e, "hipSetDevice");
+  const bool dev = (c->batch_scan.ptr_flags & RKN_PTR_DEVICE) != 0;
+  const size_t ne = (size_t)c->n_events;
+  int64_t* d_idx = index;
+  double* d_sc = score;
+  double* d_seed = seeds5;
+  if (!dev) {
+    if ((e = c->sel_idx.ensure(sizeof(int64_t) * ne * k)) != hipSuccess ||
+        (e = c->sel_sc.ensure(sizeof(double) * ne * k)) != hipSuccess ||
+        (e = c->sel_seed.ensure(sizeof(double) * ne * k * 5)) != hipSuccess)
+      return berr(c, e, "batch topk alloc");
+    d_idx = c->sel_idx.as<int64_t>();
+    d_sc = c->sel_sc.as<double>();
+    d_seed = seeds5 ? c->sel_seed.as<double>() : nullptr;
+  }
+  // after the expansion, the first n_events entries of the scratch hold each event's
+  // first window; counts[0] is the window total
+  e = launch_topk(c, c->b_score.as<double>(), c->b_ev_seed.as<long long>(), c->b_windows.as<WindowDev>(),
+                  c->b_ev_scratch.as<int32_t>(), c->n_events, c->b_counts.as<int32_t>(), k, d_idx, d_sc, d_seed);
+  if (e != hipSuccess) return berr(c, e, "batch topk");
+  if (!dev) {
+    if ((e = hipMemcpyAsync(index, d_idx, sizeof(int64_t) * ne * k, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(score, d_sc, sizeof(double) * ne * k, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (seeds5 && (e = hipMemcpyAsync(seeds5, d_seed, sizeof(double) * ne * k * 5, hipMemcpyDeviceToHost,
+                                       c->stream)) != hipSuccess) ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+      return berr(c, e, "batch topk copy");
+  }
   return RKN_OK;
 }
 
 rkn_status rkn_batch_info(rkn_ctx* c, int32_t* n_windows, int64_t* n_seeds, float* ms_hough, float* ms_scan) {
   if (!c) return RKN_E_ARG;
-  if (!c->batch_ready) {
-    c->err = "batch: nothing planned";
+  if (!c->batch_ready || !c->batch_launched) {
+    c->err = "batch: nothing launched";
     return RKN_E_STATE;
   }
   hipError_t e;

@@ -61,6 +61,23 @@ struct WindowDev {
   int32_t event;
 };
 
+// Seed k of a window's implicit grid (theta slowest, pz fastest): per dimension
+// centre - half_width + 2 half_width i / (count - 1), or the centre when count is 1.
+__device__ __forceinline__ void window_seed(const WindowDev& W, int64_t k, double v[5]) {
+  int64_t kd[5];
+#pragma unroll
+  for (int d = 4; d >= 0; --d) {
+    const int64_t n = W.count[d];
+    kd[d] = k % n;
+    k /= n;
+  }
+#pragma unroll
+  for (int d = 0; d < 5; ++d)
+    v[d] = W.count[d] <= 1 ? W.center[d]
+                           : W.center[d] - W.half_width[d] +
+                                 2.0 * W.half_width[d] * (double)kd[d] / (double)(W.count[d] - 1);
+}
+
 constexpr int kMaxCand = 64;     // Hough candidates kept per event, upper bound
 
 struct HoughDev {
@@ -115,15 +132,18 @@ struct rkn_ctx {
   std::vector<int32_t> h_ev_off;
   rkn::DevBuf ev_off, hits32, hits64, layer_off, ev_maxdrift;
   rkn::DevBuf hits_wire;             // int32 wire id per hit, upload order
+  rkn::DevBuf hits_orig;             // int32 original index within its event, per layer-ordered hit
   rkn::DevBuf hough_acc, hough_max, hough_cand_n, hough_cand, hough_slots, hough_nsel;
 
   // per-call work buffers
   rkn::DevBuf windows, tiles, ev_tiles, parts, counter, mscratch, out_score, out_nin, out_best_i,
       out_best_e, trace_buf, seeds_buf, perm_buf;
+  rkn::DevBuf sel_seg, sel_win, sel_idx, sel_sc, sel_seed;   // per-event top-k selection
   std::vector<rkn::DevBuf> extra;
 
   // batched path (planned once, launched as captured graphs)
   bool batch_ready = false;
+  bool batch_launched = false;       // results exist (set by rkn_batch_launch)
   rkn_scan_params batch_scan{};
   rkn::HoughDev batch_hough{};
   int64_t batch_max_tiles = 0, batch_max_seeds = 0;
@@ -132,6 +152,29 @@ struct rkn_ctx {
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr;
   rkn::DevBuf b_windows, b_tiles, b_ev_tiles, b_counts, b_ev_seed, b_score, b_nin, b_best_i, b_best_e,
       b_ev_scratch;
+  // the scan's scratch of the captured graph is private to it; the Hough buffers are
+  // shared with the eager Hough calls, so their addresses are recorded at capture and
+  // checked before each replay
+  rkn::DevBuf b_slab, b_parts, b_counter;
+  void* b_hough_ptrs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+
+  // refinement (refine.hip): seeds grouped by event, inlier sets fixed at setup
+  bool r_ready = false;
+  rkn_scan_params r_params{};
+  int64_t r_n = 0, r_ntiles = 0, r_ntiles6 = 0;
+  int r_ckpt = 64, r_nckpt = 0;
+  rkn::DevBuf r_seeds, r_seeds0, r_trials, r_event, r_tiles, r_tiles6, r_ident, r_base6, r_mask, r_resid,
+      r_argmin, r_resid6, r_argmin6, r_phi, r_phi6, r_phicur, r_tape, r_segbuf, r_list, r_grad, r_jtj, r_cgrad,
+      r_slab, r_counter;
+
+  rkn::DevBuf* refine_buffers_[24] = {&r_seeds, &r_seeds0, &r_trials, &r_event,  &r_tiles,  &r_tiles6,
+                                      &r_ident, &r_base6,  &r_mask,   &r_resid,  &r_argmin, &r_resid6,
+                                      &r_argmin6, &r_phi,  &r_phi6,   &r_phicur, &r_tape,   &r_segbuf,
+                                      &r_list,  &r_grad,   &r_jtj,    &r_cgrad,  &r_slab,   &r_counter};
+  void refine_release() {
+    for (rkn::DevBuf* b : refine_buffers_) b->release();
+    r_ready = false;
+  }
 
   bool set_err(const std::string& s) {
     err = s;
@@ -158,13 +201,27 @@ rkn_status make_hough_dev(rkn_ctx* c, const rkn_hough_params* p, HoughDev& h);
 hipError_t ensure_hough_buffers(rkn_ctx* c, const HoughDev& h);
 hipError_t queue_hough_all(rkn_ctx* c, const HoughDev& h);
 
+// Refinement forward pass (scan kernel in its second mode) over explicit seeds.
+hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
+                             const double* d_seeds5, const int64_t* d_perm, const int64_t* d_base_of,
+                             uint8_t* d_mask, int define_mask, float* d_resid, int32_t* d_argmin, double* d_phi,
+                             float* d_tape, int ckpt, int n_ckpt, int64_t n_pos);
+
 // Seeds per tile (= lanes per workgroup) of the scan configuration for p.
 int scan_tile(const rkn_ctx* c, const rkn_scan_params* p);
 
 // Release the batched path's graphs, events and buffers (batch.hip).
 void batch_release(rkn_ctx* c);
 
-// Scan launch whose tile count is read from device memory (batched path).
+// The k lowest-score seeds of each of n_seg events (select.hip): seeds of event e
+// are d_score[d_seg_off[e] .. d_seg_off[e+1]) and come from windows
+// d_win_off[e] .. (e + 1 < n_seg ? d_win_off[e+1] : *d_win_total), in order.
+hipError_t launch_topk(rkn_ctx* c, const double* d_score, const long long* d_seg_off, const WindowDev* d_windows,
+                       const int32_t* d_win_off, int n_seg, const int32_t* d_win_total, int k, int64_t* d_idx,
+                       double* d_sc, double* d_seed);
+
+// Scan launch whose tile count is read from device memory (batched path; uses the
+// batch's private scratch b_slab, b_parts, b_counter).
 hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_tiles, const int32_t* d_n_tiles,
                            const Tile* d_tiles, const WindowDev* d_windows, double* d_score, int32_t* d_nin,
                            int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only);

@@ -21,6 +21,8 @@
 //   * after the last block each lane forms E = sum min((D - d)^2, lambda) in FP64.
 // Both culls are exact: a pair they drop can only have a distance above
 // d + sqrt(lambda), where the term is lambda whatever the distance is.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace rkn {
@@ -54,6 +56,18 @@ struct ScanArgs {
   double* score;
   int32_t* nin;
   ArgminPart* parts;
+  // refinement forward mode (MODE 1): per output slot = scan position
+  const int32_t* hits_orig;   // original index (within its event) of each layer-ordered hit
+  const int64_t* base_of;     // scan position -> refinement seed whose inlier set applies
+  uint8_t* mask;              // [n_base][max_hits] inlier flags (original hit order)
+  int define_mask;            // 1: set mask from (D - d)^2 < lambda, 0: read it
+  float* resid;               // [n_pos][max_hits] residual D - d of inliers, NaN otherwise
+  int32_t* argmin_step;       // [n_pos][max_hits] chord index of the minimum (inliers), -1 otherwise
+  double* phi;                // [n_pos] sum of squared inlier residuals
+  float* tape;                // [n_ckpt][13][n_pos] FP32 states every ckpt steps (NULL: none)
+  int ckpt, n_ckpt;
+  int64_t n_pos;
+  int max_hits;
 };
 
 // ---------------------------------------------------------------------------------
@@ -64,7 +78,7 @@ prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__
                  const float* __restrict__ drift, const HitRec<float>* __restrict__ wire32,
                  const HitRec<double>* __restrict__ wire64, const int32_t* __restrict__ wire_layer,
                  int n_layers, HitRec<float>* __restrict__ out32, HitRec<double>* __restrict__ out64,
-                 int32_t* __restrict__ layer_off, float* __restrict__ ev_maxdrift) {
+                 int32_t* __restrict__ layer_off, float* __restrict__ ev_maxdrift, int32_t* __restrict__ orig) {
   __shared__ int s_layer[RKN_MAX_HITS_PER_EVENT];
   __shared__ int s_count[RKN_MAX_LAYERS + 1];
   __shared__ unsigned int s_max;
@@ -106,6 +120,7 @@ prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__
     r64.drift = (double)drift[base + i];
     out32[base + rank] = r32;
     out64[base + rank] = r64;
+    orig[base + rank] = i;
   }
 }
 
@@ -115,7 +130,7 @@ hipError_t launch_prep_hits(rkn_ctx* c, const int32_t* d_wire_id, const float* d
                      c->ev_off.as<int32_t>(), d_wire_id, d_drift, c->wire32.as<HitRec<float>>(),
                      c->wire64.as<HitRec<double>>(), c->wire_layer.as<int32_t>(), c->n_layers,
                      c->hits32.as<HitRec<float>>(), c->hits64.as<HitRec<double>>(),
-                     c->layer_off.as<int32_t>(), c->ev_maxdrift.as<float>());
+                     c->layer_off.as<int32_t>(), c->ev_maxdrift.as<float>(), c->hits_orig.as<int32_t>());
   return hipGetLastError();
 }
 
@@ -144,10 +159,10 @@ __device__ __forceinline__ R load_coherent(const R* p) {
 }
 
 // Dense pass over a wave's work list: item = (lane << 16) | hit.
-template <typename R, int B, int TILE>
+template <typename R, int B, int TILE, int MODE, typename S>
 __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, const R* pts,
-                                            const HitRec<R>* s_hits, R* slab, int wave, int lane,
-                                            int nb) {
+                                            const HitRec<R>* s_hits, S* slab, int wave, int lane,
+                                            int nb, int step0) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -157,28 +172,42 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
     const HitRec<R> w = s_hits[hh];
     R px = pts[0 * 64 + s], py = pts[1 * 64 + s], pz = pts[2 * 64 + s];
     R dmin = (R)INFINITY;
+    int jmin = 0;
 #pragma unroll
     for (int j = 1; j <= B; ++j) {
       if (j <= nb) {
         const R qx = pts[(j * 3 + 0) * 64 + s], qy = pts[(j * 3 + 1) * 64 + s],
                 qz = pts[(j * 3 + 2) * 64 + s];
         const R d2 = seg_wire_d2<R>(px, py, pz, qx, qy, qz, w.mx, w.my, w.mz, w.ux, w.uy, w.uz, w.L);
-        dmin = d2 < dmin ? d2 : dmin;
+        if (d2 < dmin) {
+          dmin = d2;
+          jmin = j - 1;
+        }
         px = qx;
         py = qy;
         pz = qz;
       }
     }
-    atomic_min_nonneg(slab + (size_t)hh * TILE + wave * 64 + s, dmin);
+    if constexpr (MODE == 0) {
+      atomic_min_nonneg(slab + (size_t)hh * TILE + wave * 64 + s, dmin);
+    } else {
+      // (distance bits, chord index): the minimum distance, then the lowest chord
+      const unsigned long long key = ((unsigned long long)__float_as_uint((float)dmin) << 32) |
+                                     (unsigned long long)(unsigned)(step0 + jmin);
+      atomicMin(reinterpret_cast<unsigned long long*>(slab + (size_t)hh * TILE + wave * 64 + s), key);
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R, int FIELD, int B, int WAVES>
+template <typename R, int FIELD, int B, int WAVES, int MODE>
 __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   constexpr int TILE = 64 * WAVES;
+  // MODE 0: the scan (score E). MODE 1: the refinement forward pass (FP32 only):
+  // argmin chords, checkpoints and inlier residuals.
+  using Slab = typename std::conditional<MODE == 0, R, unsigned long long>::type;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   float2* s_field = reinterpret_cast<float2*>(smem);
   HitRec<R>* s_hits = reinterpret_cast<HitRec<R>*>(smem + a.field_bytes);
@@ -193,7 +222,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   const int64_t n_tiles = a.n_tiles_dev ? (int64_t)*a.n_tiles_dev : a.n_tiles;
   R* pts = s_pts + wave * (B + 1) * 3 * 64;
   uint32_t* items = s_items + wave * kCap;
-  R* slab = reinterpret_cast<R*>(a.mscratch) + (size_t)blockIdx.x * a.slab_stride;
+  Slab* slab = reinterpret_cast<Slab*>(a.mscratch) + (size_t)blockIdx.x * a.slab_stride;
   const R h = (R)a.h;
   const double lam = a.lambda;
   int cur_event = -1;
@@ -248,21 +277,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         for (int d = 0; d < 5; ++d) v[d] = a.seeds5[pos * 5 + d];
         gidx = a.perm[pos];
       } else {
-        const WindowDev& W = a.windows[t.window];
-        int64_t k = t.start + (in_tile ? tid : 0);
-        int64_t kd[5];
-#pragma unroll
-        for (int d = 4; d >= 0; --d) {
-          const int64_t n = W.count[d];
-          kd[d] = k % n;
-          k /= n;
-        }
-#pragma unroll
-        for (int d = 0; d < 5; ++d) {
-          v[d] = W.count[d] <= 1 ? W.center[d]
-                                 : W.center[d] - W.half_width[d] +
-                                       2.0 * W.half_width[d] * (double)kd[d] / (double)(W.count[d] - 1);
-        }
+        window_seed(a.windows[t.window], t.start + (in_tile ? tid : 0), v);
       }
       const double pm = sqrt(v[2] * v[2] + v[3] * v[3] + v[4] * v[4]);
       valid = valid && (pm >= 1e-3);
@@ -277,7 +292,12 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       st.cx = st.cy = st.cz = (R)0;
       st.ctx = st.cty = st.ctz = (R)0;
     }
-    for (int i = 0; i < nh; ++i) slab[(size_t)i * TILE + tid] = (R)INFINITY;
+    for (int i = 0; i < nh; ++i) {
+      if constexpr (MODE == 0)
+        slab[(size_t)i * TILE + tid] = (R)INFINITY;
+      else
+        slab[(size_t)i * TILE + tid] = 0xffffffffffffffffULL;
+    }
     __threadfence_block();
     __syncthreads();
 
@@ -286,6 +306,17 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     for (int blk = 0; blk < nblocks; ++blk) {
       const int nb = min(B, a.n_steps - blk * B);
       const int jc = nb / 2;
+      if constexpr (MODE == 1) {
+        const int step = blk * B;
+        if (a.tape && in_tile && step % a.ckpt == 0) {
+          float* tp = a.tape + (size_t)(step / a.ckpt) * 13 * a.n_pos + gidx;
+          const float v13[13] = {(float)st.x, (float)st.y, (float)st.z, (float)st.cx, (float)st.cy, (float)st.cz,
+                                 (float)st.tx, (float)st.ty, (float)st.tz, (float)st.ctx, (float)st.cty,
+                                 (float)st.ctz, (float)st.lam};
+#pragma unroll
+          for (int q = 0; q < 13; ++q) tp[(size_t)q * a.n_pos] = v13[q];
+        }
+      }
       pts[0 * 64 + lane] = st.x;
       pts[1 * 64 + lane] = st.y;
       pts[2 * 64 + lane] = st.z;
@@ -331,15 +362,48 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
           n_items += (int)__popcll(m);
           if (n_items > kCap - 64) {
-            flush_items<R, B, TILE>(items, n_items, pts, s_hits, slab, wave, lane, nb);
+            flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B);
             n_items = 0;
           }
         }
       }
-      if (n_items) flush_items<R, B, TILE>(items, n_items, pts, s_hits, slab, wave, lane, nb);
+      if (n_items) flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B);
     }
     __threadfence();
 
+    if constexpr (MODE == 1) {
+      // ---- refinement outputs: inlier residuals (original hit order), argmin chords
+      if (in_tile) {
+        const int64_t base = a.base_of ? a.base_of[gidx] : gidx;
+        uint8_t* mrow = a.mask + (size_t)base * a.max_hits;
+        float* rrow = a.resid + (size_t)gidx * a.max_hits;
+        int32_t* arow = a.argmin_step + (size_t)gidx * a.max_hits;
+        double ph = 0.0;
+        for (int i = 0; i < nh; ++i) {
+          const unsigned long long key = load_coherent(slab + (size_t)i * TILE + tid);
+          const float d2 = __uint_as_float((unsigned)(key >> 32));
+          const double r = sqrt((double)d2) - (double)s_hits[i].drift;
+          const int o = a.hits_orig[hbase + i];
+          bool in;
+          if (a.define_mask) {
+            in = valid && (r * r < lam);
+            mrow[o] = in ? 1 : 0;
+          } else {
+            in = valid && mrow[o] != 0;
+          }
+          rrow[o] = in ? (float)r : NAN;
+          arow[o] = in ? (int32_t)(unsigned)(key & 0xffffffffu) : -1;
+          if (in) ph += r * r;
+        }
+        for (int i = nh; i < a.max_hits; ++i) {
+          rrow[i] = NAN;
+          arow[i] = -1;
+        }
+        a.phi[gidx] = valid ? ph : INFINITY;
+      }
+      __syncthreads();
+      continue;
+    }
     // ---- score (Eq. 1), in FP64 ---------------------------------------------------
     double E = 0.0;
     int cnt = 0;
@@ -429,8 +493,8 @@ event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restr
   }
 }
 
-template <typename R, int FIELD, int B, int WAVES>
-static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only) {
+template <typename R, int FIELD, int B, int WAVES, int MODE = 0>
+static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only, DevBuf& slab_buf) {
   constexpr int TILE = 64 * WAVES;
   const int hits_bytes = ((c->max_hits_event * (int)sizeof(HitRec<R>)) + 255) & ~255;
   const int field_bytes = FIELD == 1 ? ((c->nr * c->nz * (int)sizeof(float2)) + 255) & ~255 : 0;
@@ -439,7 +503,7 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   const size_t smem = (size_t)field_bytes + hits_bytes + kTabBins * 4 + WAVES * (B + 1) * 3 * 64 * sizeof(R) +
                       WAVES * kCap * sizeof(uint32_t);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
-  auto kern = scan_kernel<R, FIELD, B, WAVES>;
+  auto kern = scan_kernel<R, FIELD, B, WAVES, MODE>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -450,9 +514,9 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   if (grid > max_tiles) grid = max_tiles;
   if (grid < 1) grid = 1;
   a.slab_stride = (int64_t)(c->max_hits_event > 0 ? c->max_hits_event : 1) * TILE;
-  e = c->mscratch.ensure((size_t)grid * a.slab_stride * sizeof(R));
+  e = slab_buf.ensure((size_t)grid * a.slab_stride * (MODE == 0 ? sizeof(R) : sizeof(unsigned long long)));
   if (e != hipSuccess) return e;
-  a.mscratch = c->mscratch.p;
+  a.mscratch = slab_buf.p;
   if (alloc_only) return hipSuccess;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, c->stream, a.tile_counter);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TILE), smem, c->stream, a);
@@ -466,16 +530,16 @@ int scan_tile(const rkn_ctx* c, const rkn_scan_params* p) {
 }
 
 static hipError_t dispatch_scan(rkn_ctx* c, const rkn_scan_params* p, ScanArgs& a, int64_t max_tiles,
-                                bool alloc_only) {
+                                bool alloc_only, DevBuf& slab) {
   const int B = p->block_steps;
   if (p->precision == 64)
-    return c->field_kind == 0 ? launch_scan_t<double, 0, 4, 4>(c, a, max_tiles, alloc_only)
-                              : launch_scan_t<double, 1, 4, 4>(c, a, max_tiles, alloc_only);
+    return c->field_kind == 0 ? launch_scan_t<double, 0, 4, 4>(c, a, max_tiles, alloc_only, slab)
+                              : launch_scan_t<double, 1, 4, 4>(c, a, max_tiles, alloc_only, slab);
   if (c->field_kind == 0)
-    return B == 4 ? launch_scan_t<float, 0, 4, 4>(c, a, max_tiles, alloc_only)
-                  : launch_scan_t<float, 0, 8, 4>(c, a, max_tiles, alloc_only);
-  return B == 4 ? launch_scan_t<float, 1, 4, 8>(c, a, max_tiles, alloc_only)
-                : launch_scan_t<float, 1, 8, 8>(c, a, max_tiles, alloc_only);
+    return B == 4 ? launch_scan_t<float, 0, 4, 4>(c, a, max_tiles, alloc_only, slab)
+                  : launch_scan_t<float, 0, 8, 4>(c, a, max_tiles, alloc_only, slab);
+  return B == 4 ? launch_scan_t<float, 1, 4, 8>(c, a, max_tiles, alloc_only, slab)
+                : launch_scan_t<float, 1, 8, 8>(c, a, max_tiles, alloc_only, slab);
 }
 
 FieldDev field_dev(const rkn_ctx* c) {
@@ -493,8 +557,51 @@ FieldDev field_dev(const rkn_ctx* c) {
   return f;
 }
 
+// Refinement forward pass over explicit seeds (FP32, block of 8 steps).
+hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
+                             const double* d_seeds5, const int64_t* d_perm, const int64_t* d_base_of,
+                             uint8_t* d_mask, int define_mask, float* d_resid, int32_t* d_argmin, double* d_phi,
+                             float* d_tape, int ckpt, int n_ckpt, int64_t n_pos) {
+  hipError_t e = c->r_counter.ensure(64);
+  if (e != hipSuccess) return e;
+  ScanArgs a{};
+  a.field = field_dev(c);
+  a.hits32 = c->hits32.as<HitRec<float>>();
+  a.hits64 = c->hits64.as<HitRec<double>>();
+  a.ev_off = c->ev_off.as<int32_t>();
+  a.layer_off = c->layer_off.as<int32_t>();
+  a.layer_r = c->layer_r.as<float2>();
+  a.ev_maxdrift = c->ev_maxdrift.as<float>();
+  a.n_layers = c->n_layers;
+  a.tiles = d_tiles;
+  a.n_tiles = n_tiles;
+  a.seeds5 = d_seeds5;
+  a.perm = d_perm;
+  a.tile_counter = c->r_counter.as<int>();
+  a.R0 = p->R0;
+  a.charge = p->charge;
+  a.h = p->step_mm;
+  a.lambda = p->lambda_mm2;
+  a.n_steps = p->n_steps;
+  a.hits_orig = c->hits_orig.as<int32_t>();
+  a.base_of = d_base_of;
+  a.mask = d_mask;
+  a.define_mask = define_mask;
+  a.resid = d_resid;
+  a.argmin_step = d_argmin;
+  a.phi = d_phi;
+  a.tape = d_tape;
+  a.ckpt = ckpt;
+  a.n_ckpt = n_ckpt;
+  a.n_pos = n_pos;
+  a.max_hits = c->max_hits_event > 0 ? c->max_hits_event : 1;
+  if (n_tiles == 0) return hipSuccess;
+  return c->field_kind == 0 ? launch_scan_t<float, 0, 8, 4, 1>(c, a, n_tiles, false, c->r_slab)
+                            : launch_scan_t<float, 1, 8, 8, 1>(c, a, n_tiles, false, c->r_slab);
+}
+
 static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_tiles, const WindowDev* d_windows,
-                          double* d_score, int32_t* d_nin) {
+                          double* d_score, int32_t* d_nin, DevBuf& parts, DevBuf& counter) {
   ScanArgs a{};
   a.field = field_dev(c);
   a.hits32 = c->hits32.as<HitRec<float>>();
@@ -506,7 +613,7 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   a.n_layers = c->n_layers;
   a.tiles = d_tiles;
   a.windows = d_windows;
-  a.tile_counter = c->counter.as<int>();
+  a.tile_counter = counter.as<int>();
   a.R0 = p->R0;
   a.charge = p->charge;
   a.h = p->step_mm;
@@ -514,7 +621,7 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   a.n_steps = p->n_steps;
   a.score = d_score;
   a.nin = d_nin;
-  a.parts = c->parts.as<ArgminPart>();
+  a.parts = parts.as<ArgminPart>();
   return a;
 }
 
@@ -526,12 +633,12 @@ hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, co
   if (e != hipSuccess) return e;
   e = c->counter.ensure(64);
   if (e != hipSuccess) return e;
-  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin);
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, c->parts, c->counter);
   a.n_tiles = n_tiles;
   a.seeds5 = d_seeds5;
   a.perm = d_perm;
   if (n_tiles > 0) {
-    e = dispatch_scan(c, p, a, n_tiles, false);
+    e = dispatch_scan(c, p, a, n_tiles, false, c->mscratch);
     if (e != hipSuccess) return e;
   }
   if (c->n_events > 0) {
@@ -544,17 +651,17 @@ hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, co
 hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_tiles, const int32_t* d_n_tiles,
                            const Tile* d_tiles, const WindowDev* d_windows, double* d_score, int32_t* d_nin,
                            int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only) {
-  hipError_t e = c->parts.ensure(sizeof(ArgminPart) * (size_t)(max_tiles > 0 ? max_tiles : 1));
+  hipError_t e = c->b_parts.ensure(sizeof(ArgminPart) * (size_t)(max_tiles > 0 ? max_tiles : 1));
   if (e != hipSuccess) return e;
-  e = c->counter.ensure(64);
+  e = c->b_counter.ensure(64);
   if (e != hipSuccess) return e;
-  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin);
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, c->b_parts, c->b_counter);
   a.n_tiles = max_tiles;
   a.n_tiles_dev = d_n_tiles;
-  e = dispatch_scan(c, p, a, max_tiles, alloc_only);
+  e = dispatch_scan(c, p, a, max_tiles, alloc_only, c->b_slab);
   if (e != hipSuccess || alloc_only) return e;
   hipLaunchKernelGGL(event_argmin_kernel, dim3(c->n_events), dim3(256), 0, c->stream,
-                     c->parts.as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
+                     c->b_parts.as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ RKN_E_UNSUPPORTED = -6
 RKN_PTR_DEVICE = 1
 RKN_MAX_HITS_PER_EVENT = 512
 RKN_MAX_LAYERS = 64
+RKN_TOPK_MAX = 16
 
 STATUS_NAMES = {0: "RKN_OK", -1: "RKN_E_ARG", -2: "RKN_E_STATE", -3: "RKN_E_NOMEM",
                 -4: "RKN_E_DEVICE", -5: "RKN_E_CAPACITY", -6: "RKN_E_UNSUPPORTED"}
@@ -80,6 +81,12 @@ _SIGS = {
     "rkn_batch_launch": (C.c_int32, [_P, _P, _P]),
     "rkn_batch_info": (C.c_int32, [_P, _P, _P, _P, _P]),
     "rkn_batch_results": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P, _P]),
+    "rkn_batch_topk": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "rkn_scan_windows_topk": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, _P, _P, _P]),
+    "rkn_refine_setup": (C.c_int32, [_P, _P, C.c_int64, _P, _P, C.c_int32]),
+    "rkn_residuals_fwd": (C.c_int32, [_P, _P, _P, _P]),
+    "rkn_adjoint_bwd": (C.c_int32, [_P, _P, _P, _P, _P]),
+    "rkn_gn_refine": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
 }
 
 _lib = None
@@ -245,6 +252,20 @@ def rkn_scan_windows(ctx, p: rkn_scan_params, windows, score=None, n_in=None, be
     return score, n_in, best_index, best_score
 
 
+def rkn_scan_windows_topk(ctx, p: rkn_scan_params, windows, k, index=None, score=None, seeds5=None,
+                          n_events=None):
+    """k best seeds per event of a window scan; host outputs are allocated when None
+    (n_events required then)."""
+    if index is None:
+        index = np.zeros((n_events, k), np.int64)
+        score = np.zeros((n_events, k))
+        seeds5 = np.zeros((n_events, k, 5))
+    w = windows_to_c(windows)
+    _check(ctx, load_library().rkn_scan_windows_topk(ctx, C.byref(p), len(windows), w, int(k), _ptr(index),
+                                                     _ptr(score), _ptr(seeds5)))
+    return index, score, seeds5
+
+
 def rkn_scan_seeds(ctx, p: rkn_scan_params, seed_event, seeds5, score=None, n_in=None, best_index=None,
                    best_score=None):
     se = _host(seed_event, np.int32)
@@ -274,6 +295,15 @@ def rkn_batch_launch(ctx, best_index=None, best_score=None):
     return best_index, best_score
 
 
+def rkn_batch_topk(ctx, k, index=None, score=None, seeds5=None, n_events=None):
+    if index is None:
+        index = np.zeros((n_events, k), np.int64)
+        score = np.zeros((n_events, k))
+        seeds5 = np.zeros((n_events, k, 5))
+    _check(ctx, load_library().rkn_batch_topk(ctx, int(k), _ptr(index), _ptr(score), _ptr(seeds5)))
+    return index, score, seeds5
+
+
 def rkn_batch_info(ctx):
     """(n_windows, n_seeds, ms_hough, ms_scan) of the last batch launch."""
     nw = C.c_int32(); ns = C.c_int64(); th = C.c_float(); ts = C.c_float()
@@ -295,11 +325,37 @@ def rkn_batch_results(ctx, n_events: int, want_scores: bool = True):
         (nin[:ns] if want_scores else None), off
 
 
+def rkn_refine_setup(ctx, p: rkn_scan_params, seed_event, seeds5, ckpt_every: int = 64) -> None:
+    se = _host(seed_event, np.int32)
+    s5 = np.ascontiguousarray(np.asarray(seeds5, np.float64).reshape(-1, 5))
+    _check(ctx, load_library().rkn_refine_setup(ctx, C.byref(p), se.size, _ptr(se), _ptr(s5), int(ckpt_every)))
+
+
+def rkn_residuals_fwd(ctx, seeds5=None, resid=None, phi=None):
+    s5 = None if seeds5 is None else (seeds5 if hasattr(seeds5, "data_ptr") else
+                                      np.ascontiguousarray(np.asarray(seeds5, np.float64).reshape(-1, 5)))
+    _check(ctx, load_library().rkn_residuals_fwd(ctx, _ptr(s5), _ptr(resid), _ptr(phi)))
+    return resid, phi
+
+
+def rkn_adjoint_bwd(ctx, d_resid=None, d_seed=None, JtJ=None, Jtr=None):
+    dr = None if d_resid is None else (d_resid if hasattr(d_resid, "data_ptr") else _host(d_resid, np.float32))
+    _check(ctx, load_library().rkn_adjoint_bwd(ctx, _ptr(dr), _ptr(d_seed), _ptr(JtJ), _ptr(Jtr)))
+    return d_seed, JtJ, Jtr
+
+
+def rkn_gn_refine(ctx, iters, scale, seeds_out=None, phi=None):
+    sc = _host(scale, np.float64)
+    _check(ctx, load_library().rkn_gn_refine(ctx, int(iters), _ptr(sc), _ptr(seeds_out), _ptr(phi)))
+    return seeds_out, phi
+
+
 class Context:
     """Convenience owner of an rkn_ctx (destroyed with the object)."""
 
     def __init__(self, device: int = 0, stream: int | None = None):
         self.ctx = rkn_create(device, stream)
+        self.stream = stream
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
@@ -324,3 +380,6 @@ class Context:
 
     def upload_hits(self, ev_off, wire_id, drift):
         rkn_upload_hits(self.ctx, ev_off, wire_id, drift)
+        off = np.asarray(ev_off)
+        self.n_events = off.size - 1
+        self.max_hits = int(np.diff(off).max(initial=0))
