@@ -222,6 +222,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement comparison")
+    ap.add_argument("--block-steps", type=int, default=0, help="RKN steps per cull block (0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -254,7 +255,7 @@ def main():
     ctx.upload_field(field)
     ctx.upload_hits(off, wid, dr)
     lam = 64.0
-    sp = rk.make_scan_params(n_steps=args.rkn_steps, precision=32, lambda_mm2=lam)
+    sp = rk.make_scan_params(n_steps=args.rkn_steps, precision=32, lambda_mm2=lam, block_steps=args.block_steps)
     hp = cfg4_hough_params(field)
     rk.rkn_batch_plan(ctx.ctx, hp, sp)
     ne = args.events

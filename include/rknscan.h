@@ -159,7 +159,8 @@ typedef struct {
   int32_t n_steps;    /* fixed number of RKN steps per seed, >= 1                  */
   int32_t precision;  /* 32: FP32 propagation and distances, FP64 score; 64: FP64  */
   int32_t ptr_flags;  /* RKN_PTR_DEVICE: outputs are device pointers               */
-  int32_t block_steps;/* steps per DCA block (0 = default); tuning knob            */
+  int32_t block_steps;/* 0 (= 8), 4, 6 or 8: RKN steps per cull/DCA block; with the  */
+                      /* FP32 field map it also sets the workgroup (16/12/8 waves) */
 } rkn_scan_params;
 
 /* Score every seed of the windows: E = sum over the event's hits of
@@ -210,6 +211,17 @@ rkn_status rkn_trace(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, co
  * seeds) and capture the graphs. sp->ptr_flags chooses host or device outputs of
  * rkn_batch_launch. */
 rkn_status rkn_batch_plan(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp);
+
+/* Autotuner of the batched path: plans the batch with each block size of
+ * {4, 6, 8} RKN steps (which with the FP32 field map also sets the workgroup to
+ * 16, 12 or 8 waves, i.e. the seeds per tile), times the scan over the tiles of the
+ * first sample_events events on the current hits (HIP events, best of reps), and
+ * leaves the batch planned with the fastest, as rkn_batch_plan with that
+ * block_steps would. chosen (may be NULL): that block size; ms[3] (may be NULL):
+ * the sample times of 4, 6 and 8 (+inf where a shape does not fit). sp->block_steps
+ * is ignored. */
+rkn_status rkn_batch_autotune(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp,
+                              int32_t sample_events, int32_t reps, int32_t *chosen, float *ms);
 
 /* Replay the graphs on the current hits; best_index/best_score per event (global
  * seed index of the batch, -1/+inf for an event without windows) as in

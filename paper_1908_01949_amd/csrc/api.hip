@@ -50,8 +50,8 @@ rkn_status check_scan_params(rkn_ctx* c, const rkn_scan_params* p) {
   if (!is_fin(p->lambda_mm2) || p->lambda_mm2 < 0) return arg_err(c, "lambda_mm2 must be finite and >= 0");
   if (p->n_steps < 1) return arg_err(c, "n_steps must be >= 1");
   if (p->precision != 32 && p->precision != 64) return arg_err(c, "precision must be 32 or 64");
-  if (p->block_steps != 0 && p->block_steps != 4 && p->block_steps != 8)
-    return arg_err(c, "block_steps must be 0, 4 or 8");
+  if (p->block_steps != 0 && p->block_steps != 4 && p->block_steps != 6 && p->block_steps != 8)
+    return arg_err(c, "block_steps must be 0, 4, 6 or 8");
   if (p->ptr_flags & ~RKN_PTR_DEVICE) return arg_err(c, "unknown ptr_flags bits");
   return RKN_OK;
 }
@@ -340,7 +340,7 @@ static rkn_status run_scan(rkn_ctx* c, const rkn_scan_params* p, std::vector<rkn
     d_be = c->out_best_e.as<double>();
   }
   rkn_scan_params q = *p;
-  if (q.block_steps == 0) q.block_steps = 8;
+  q.block_steps = rkn::resolve_block_steps(c, &q);
   hipError_t e = rkn::launch_scan(c, &q, (int64_t)tiles.size(), c->tiles.as<rkn::Tile>(),
                                   c->windows.as<rkn::WindowDev>(), d_seeds5, d_perm, d_score, d_nin,
                                   d_bi, d_be, c->ev_tiles.as<int32_t>());
@@ -472,7 +472,7 @@ rkn_status rkn_scan_windows_topk(rkn_ctx* c, const rkn_scan_params* p, int32_t n
     d_seed = seeds5 ? c->sel_seed.as<double>() : nullptr;
   }
   rkn_scan_params q = *p;
-  if (q.block_steps == 0) q.block_steps = 8;
+  q.block_steps = rkn::resolve_block_steps(c, &q);
   hipError_t e = rkn::launch_scan(c, &q, (int64_t)tiles.size(), c->tiles.as<rkn::Tile>(),
                                   c->windows.as<rkn::WindowDev>(), nullptr, nullptr, c->out_score.as<double>(),
                                   nullptr, c->out_best_i.as<int64_t>(), c->out_best_e.as<double>(),

@@ -144,7 +144,7 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
   if (st != RKN_OK) return st;
   if (!sp || sp->n_steps < 1 || !(sp->step_mm > 0) || !(sp->lambda_mm2 >= 0) || !(sp->R0 > 0) ||
       !std::isfinite(sp->charge) || sp->charge == 0 || (sp->precision != 32 && sp->precision != 64) ||
-      (sp->block_steps != 0 && sp->block_steps != 4 && sp->block_steps != 8) ||
+      (sp->block_steps != 0 && sp->block_steps != 4 && sp->block_steps != 6 && sp->block_steps != 8) ||
       (sp->ptr_flags & ~RKN_PTR_DEVICE)) {
     c->err = "batch: invalid scan parameters";
     return RKN_E_ARG;
@@ -162,7 +162,7 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
   const int64_t max_windows = (int64_t)ne * h.max_cand;
   c->batch_max_seeds = max_windows * per_window;
   c->batch_scan = *sp;
-  if (c->batch_scan.block_steps == 0) c->batch_scan.block_steps = 8;
+  c->batch_scan.block_steps = resolve_block_steps(c, &c->batch_scan);
   const int tile = scan_tile(c, &c->batch_scan);
   c->batch_max_tiles = max_windows * ((per_window + tile - 1) / tile);
   if (c->batch_max_tiles > (int64_t(1) << 31) || c->batch_max_seeds > (int64_t(1) << 40)) {
@@ -170,7 +170,7 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
     return RKN_E_CAPACITY;
   }
   c->batch_scan = *sp;
-  if (c->batch_scan.block_steps == 0) c->batch_scan.block_steps = 8;
+  c->batch_scan.block_steps = resolve_block_steps(c, &c->batch_scan);
   c->batch_hough = h;
   if ((e = ensure_hough_buffers(c, h)) != hipSuccess) return berr(c, e, "batch alloc");
   if ((e = c->b_windows.ensure(sizeof(WindowDev) * std::max<int64_t>(max_windows, 1))) != hipSuccess ||
@@ -235,6 +235,57 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
   hough_ptrs(c, c->b_hough_ptrs);
   c->batch_ready = true;
   return RKN_OK;
+}
+
+rkn_status rkn_batch_autotune(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan_params* sp,
+                              int32_t sample_events, int32_t reps, int32_t* chosen, float* ms) {
+  if (!c) return RKN_E_ARG;
+  if (!sp || sample_events < 1 || reps < 1 || reps > 100) {
+    c->err = "autotune: need scan parameters, sample_events >= 1 and reps in [1, 100]";
+    return RKN_E_ARG;
+  }
+  const int cand[3] = {4, 6, 8};
+  float best_ms = INFINITY;
+  int best = 0;
+  for (int i = 0; i < 3; ++i) {
+    if (ms) ms[i] = INFINITY;
+    rkn_scan_params q = *sp;
+    q.block_steps = cand[i];
+    rkn_status st = rkn_batch_plan(c, hp, &q);
+    if (st == RKN_E_UNSUPPORTED) continue;
+    if (st != RKN_OK) return st;
+    hipError_t e;
+    // graph A writes the tiles; the scan then runs over the first events' tiles only
+    if ((e = hipGraphLaunch(c->x_hough, c->stream)) != hipSuccess) return berr(c, e, "autotune");
+    const int k = std::min(sample_events, c->n_events);
+    float t_min = INFINITY;
+    for (int r = 0; r < reps; ++r) {
+      if ((e = hipEventRecord(c->ev_t1, c->stream)) != hipSuccess) return berr(c, e, "autotune");
+      e = launch_scan_dev(c, &c->batch_scan, c->batch_max_tiles, c->b_ev_tiles.as<int32_t>() + k,
+                          c->b_tiles.as<Tile>(), c->b_windows.as<WindowDev>(), c->b_score.as<double>(),
+                          c->b_nin.as<int32_t>(), c->b_best_i.as<int64_t>(), c->b_best_e.as<double>(),
+                          c->b_ev_tiles.as<int32_t>(), false);
+      if (e != hipSuccess) return berr(c, e, "autotune scan");
+      if ((e = hipEventRecord(c->ev_t2, c->stream)) != hipSuccess || (e = hipEventSynchronize(c->ev_t2)) != hipSuccess)
+        return berr(c, e, "autotune");
+      float t = 0.0f;
+      if ((e = hipEventElapsedTime(&t, c->ev_t1, c->ev_t2)) != hipSuccess) return berr(c, e, "autotune");
+      t_min = std::min(t_min, t);
+    }
+    if (ms) ms[i] = t_min;
+    if (t_min < best_ms) {
+      best_ms = t_min;
+      best = cand[i];
+    }
+  }
+  if (best == 0) {
+    c->err = "autotune: no block size fits the device";
+    return RKN_E_UNSUPPORTED;
+  }
+  rkn_scan_params q = *sp;
+  q.block_steps = best;
+  if (chosen) *chosen = best;
+  return rkn_batch_plan(c, hp, &q);
 }
 
 rkn_status rkn_batch_launch(rkn_ctx* c, int64_t* best_index, double* best_score) {

@@ -75,35 +75,55 @@ __device__ __forceinline__ R frcp(R x) {
 template <typename R>
 __device__ __forceinline__ void field_rz(const FieldDev& f, const float2* nodes, R x, R y, R z, R& bx, R& by,
                                          R& bz) {
-  const R r2 = x * x + y * y;
-  R r, inv_r;
   if constexpr (sizeof(R) == 4) {
-    inv_r = __builtin_amdgcn_rsqf(r2 > (R)1e-30 ? r2 : (R)1e-30);   // one transcendental
-    r = r2 * inv_r;
+    // FP32: one rsq, clamps by med3, the cell from floor in float (exact for the
+    // small integers involved), and the node index from one fma.
+    const float r2 = fmaf(x, x, y * y);
+    const float inv_r = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+    const float r = r2 * inv_r;
+    const float fnr = (float)f.nr, fnz = (float)f.nz;
+    const float u = __builtin_amdgcn_fmed3f(fmaf(r, (float)f.inv_dr, (float)(-f.r0 * f.inv_dr)), 0.0f, fnr - 1.0f);
+    const float v = __builtin_amdgcn_fmed3f(fmaf(z, (float)f.inv_dz, (float)(-f.z0 * f.inv_dz)), 0.0f, fnz - 1.0f);
+    const float fi = fminf(floorf(u), fnr - 2.0f);
+    const float fj = fminf(floorf(v), fnz - 2.0f);
+    const float a = u - fi, b = v - fj;
+    const float2* row0 = nodes + (int)fmaf(fj, fnr, fi);
+    const float2* row1 = row0 + f.nr;
+    const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
+    const float br0 = fmaf(a, n01.x - n00.x, n00.x);
+    const float br1 = fmaf(a, n11.x - n10.x, n10.x);
+    const float bz0 = fmaf(a, n01.y - n00.y, n00.y);
+    const float bz1 = fmaf(a, n11.y - n10.y, n10.y);
+    const float br = fmaf(b, br1 - br0, br0);
+    bz = fmaf(b, bz1 - bz0, bz0);
+    // on the axis x = y = 0, so B_x = B_y = 0 whatever inv_r is (finite here)
+    const float s = br * inv_r;
+    bx = s * x;
+    by = s * y;
   } else {
-    r = sqrt(r2);
-    inv_r = r > (R)1e-9 ? (R)1 / r : (R)0;
+    const R r2 = x * x + y * y;
+    const R r = sqrt(r2);
+    const R inv_r = r > (R)1e-9 ? (R)1 / r : (R)0;
+    const R u = clampv((r - (R)f.r0) * (R)f.inv_dr, (R)0, (R)(f.nr - 1));
+    const R v = clampv((z - (R)f.z0) * (R)f.inv_dz, (R)0, (R)(f.nz - 1));
+    const int iu = (int)u, jv = (int)v;
+    const int i = iu < f.nr - 2 ? iu : f.nr - 2;
+    const int j = jv < f.nz - 2 ? jv : f.nz - 2;
+    const R a = u - (R)i;
+    const R b = v - (R)j;
+    const float2* row0 = nodes + j * f.nr + i;
+    const float2* row1 = row0 + f.nr;
+    const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
+    const R br0 = (R)n00.x + a * ((R)n01.x - (R)n00.x);
+    const R br1 = (R)n10.x + a * ((R)n11.x - (R)n10.x);
+    const R bz0 = (R)n00.y + a * ((R)n01.y - (R)n00.y);
+    const R bz1 = (R)n10.y + a * ((R)n11.y - (R)n10.y);
+    const R br = br0 + b * (br1 - br0);
+    bz = bz0 + b * (bz1 - bz0);
+    const R s = br * inv_r;
+    bx = s * x;
+    by = s * y;
   }
-  const R u = clampv((r - (R)f.r0) * (R)f.inv_dr, (R)0, (R)(f.nr - 1));
-  const R v = clampv((z - (R)f.z0) * (R)f.inv_dz, (R)0, (R)(f.nz - 1));
-  const int iu = (int)u, jv = (int)v;
-  const int i = iu < f.nr - 2 ? iu : f.nr - 2;
-  const int j = jv < f.nz - 2 ? jv : f.nz - 2;
-  const R a = u - (R)i;
-  const R b = v - (R)j;
-  const float2* row0 = nodes + j * f.nr + i;
-  const float2* row1 = row0 + f.nr;
-  const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
-  const R br0 = (R)n00.x + a * ((R)n01.x - (R)n00.x);
-  const R br1 = (R)n10.x + a * ((R)n11.x - (R)n10.x);
-  const R bz0 = (R)n00.y + a * ((R)n01.y - (R)n00.y);
-  const R bz1 = (R)n10.y + a * ((R)n11.y - (R)n10.y);
-  const R br = br0 + b * (br1 - br0);
-  bz = bz0 + b * (bz1 - bz0);
-  // on the axis x = y = 0, so B_x = B_y = 0 whatever inv_r is (finite here)
-  const R s = br * inv_r;
-  bx = s * x;
-  by = s * y;
 }
 
 // Propagation state. For FP32 the position and the direction carry Kahan
@@ -177,13 +197,15 @@ __device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, const 
     field_rz(f, nodes, st.x + h2 * st.tx + hh8 * k1x, st.y + h2 * st.ty + hh8 * k1y,
              st.z + h2 * st.tz + hh8 * k1z, bx, by, bz);
     const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y, t2z = st.tz + h2 * k1z;
-    const R k2x = l * (t2y * bz - t2z * by);
-    const R k2y = l * (t2z * bx - t2x * bz);
-    const R k2z = l * (t2x * by - t2y * bx);
+    // stages 2 and 3 share the middle field: scale it by Lambda once
+    const R lbx = l * bx, lby = l * by, lbz = l * bz;
+    const R k2x = t2y * lbz - t2z * lby;
+    const R k2y = t2z * lbx - t2x * lbz;
+    const R k2z = t2x * lby - t2y * lbx;
     const R t3x = st.tx + h2 * k2x, t3y = st.ty + h2 * k2y, t3z = st.tz + h2 * k2z;
-    const R k3x = l * (t3y * bz - t3z * by);
-    const R k3y = l * (t3z * bx - t3x * bz);
-    const R k3z = l * (t3x * by - t3y * bx);
+    const R k3x = t3y * lbz - t3z * lby;
+    const R k3y = t3z * lbx - t3x * lbz;
+    const R k3z = t3x * lby - t3y * lbx;
     const R hh2 = h * h * (R)0.5;
     field_rz(f, nodes, st.x + h * st.tx + hh2 * k3x, st.y + h * st.ty + hh2 * k3y,
              st.z + h * st.tz + hh2 * k3z, bx, by, bz);

@@ -209,6 +209,8 @@ hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_til
 
 // Seeds per tile (= lanes per workgroup) of the scan configuration for p.
 int scan_tile(const rkn_ctx* c, const rkn_scan_params* p);
+// RKN steps per cull block after resolving the default (0).
+int resolve_block_steps(const rkn_ctx* c, const rkn_scan_params* p);
 
 // Release the batched path's graphs, events and buffers (batch.hip).
 void batch_release(rkn_ctx* c);

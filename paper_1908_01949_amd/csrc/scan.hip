@@ -493,6 +493,32 @@ event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restr
   }
 }
 
+// LDS bytes of one workgroup of scan_kernel<R, FIELD, B, WAVES>.
+static size_t scan_lds_bytes(const rkn_ctx* c, size_t rsize, int field, int B, int waves) {
+  const size_t hits = ((size_t)c->max_hits_event * (rsize == 4 ? sizeof(HitRec<float>) : sizeof(HitRec<double>)) +
+                       255) & ~(size_t)255;
+  const size_t fld = field == 1 ? (((size_t)c->nr * c->nz * sizeof(float2)) + 255) & ~(size_t)255 : 0;
+  return fld + hits + kTabBins * 4 + (size_t)waves * (B + 1) * 3 * 64 * rsize + (size_t)waves * kCap * 4;
+}
+
+// Steps per block; 0 picks the default: 6 for the FP32 field-map path (12-wave
+// workgroups, the fastest shape measured on the 512-event batch), else 8.
+int resolve_block_steps(const rkn_ctx* c, const rkn_scan_params* p) {
+  if (p->block_steps != 0) return p->block_steps;
+  return (p->precision == 32 && c->field_kind == 1) ? 6 : 8;
+}
+
+// Waves per workgroup. The FP32 field-map path stages the map in LDS once per
+// workgroup, so it uses the widest workgroup whose LDS fits: 16 waves with 4-step
+// blocks, 12 with 6-step blocks, 8 with 8-step blocks (falling back to 8 waves when
+// an event has too many hits for the wider shape).
+static int scan_waves(const rkn_ctx* c, int precision, int B) {
+  if (precision == 64 || c->field_kind == 0) return 4;
+  const int w = B == 4 ? 16 : B == 6 ? 12 : 8;
+  if (w > 8 && scan_lds_bytes(c, 4, 1, B, w) + 256 > (size_t)c->max_lds_block) return 8;
+  return w;
+}
+
 template <typename R, int FIELD, int B, int WAVES, int MODE = 0>
 static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only, DevBuf& slab_buf) {
   constexpr int TILE = 64 * WAVES;
@@ -500,8 +526,7 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   const int field_bytes = FIELD == 1 ? ((c->nr * c->nz * (int)sizeof(float2)) + 255) & ~255 : 0;
   a.hits_bytes = hits_bytes;
   a.field_bytes = field_bytes;
-  const size_t smem = (size_t)field_bytes + hits_bytes + kTabBins * 4 + WAVES * (B + 1) * 3 * 64 * sizeof(R) +
-                      WAVES * kCap * sizeof(uint32_t);
+  const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
   auto kern = scan_kernel<R, FIELD, B, WAVES, MODE>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -523,23 +548,29 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   return hipGetLastError();
 }
 
-// Kernel configuration per (precision, field): the field map path uses 8 waves per
-// workgroup so that the map staged in LDS serves 512 seeds.
 int scan_tile(const rkn_ctx* c, const rkn_scan_params* p) {
-  return (p->precision == 32 && c->field_kind == 1) ? 512 : 256;
+  return 64 * scan_waves(c, p->precision, p->precision == 64 ? 4 : resolve_block_steps(c, p));
 }
 
 static hipError_t dispatch_scan(rkn_ctx* c, const rkn_scan_params* p, ScanArgs& a, int64_t max_tiles,
                                 bool alloc_only, DevBuf& slab) {
-  const int B = p->block_steps;
+  const int B = resolve_block_steps(c, p);
   if (p->precision == 64)
     return c->field_kind == 0 ? launch_scan_t<double, 0, 4, 4>(c, a, max_tiles, alloc_only, slab)
                               : launch_scan_t<double, 1, 4, 4>(c, a, max_tiles, alloc_only, slab);
-  if (c->field_kind == 0)
-    return B == 4 ? launch_scan_t<float, 0, 4, 4>(c, a, max_tiles, alloc_only, slab)
-                  : launch_scan_t<float, 0, 8, 4>(c, a, max_tiles, alloc_only, slab);
-  return B == 4 ? launch_scan_t<float, 1, 4, 8>(c, a, max_tiles, alloc_only, slab)
-                : launch_scan_t<float, 1, 8, 8>(c, a, max_tiles, alloc_only, slab);
+  if (c->field_kind == 0) {
+    if (B == 4) return launch_scan_t<float, 0, 4, 4>(c, a, max_tiles, alloc_only, slab);
+    if (B == 6) return launch_scan_t<float, 0, 6, 4>(c, a, max_tiles, alloc_only, slab);
+    return launch_scan_t<float, 0, 8, 4>(c, a, max_tiles, alloc_only, slab);
+  }
+  const int W = scan_waves(c, 32, B);
+  if (B == 4)
+    return W == 16 ? launch_scan_t<float, 1, 4, 16>(c, a, max_tiles, alloc_only, slab)
+                   : launch_scan_t<float, 1, 4, 8>(c, a, max_tiles, alloc_only, slab);
+  if (B == 6)
+    return W == 12 ? launch_scan_t<float, 1, 6, 12>(c, a, max_tiles, alloc_only, slab)
+                   : launch_scan_t<float, 1, 6, 8>(c, a, max_tiles, alloc_only, slab);
+  return launch_scan_t<float, 1, 8, 8>(c, a, max_tiles, alloc_only, slab);
 }
 
 FieldDev field_dev(const rkn_ctx* c) {

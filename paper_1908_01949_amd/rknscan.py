@@ -82,6 +82,7 @@ _SIGS = {
     "rkn_batch_info": (C.c_int32, [_P, _P, _P, _P, _P]),
     "rkn_batch_results": (C.c_int32, [_P, C.c_int32, _P, _P, C.c_int64, _P, _P, _P]),
     "rkn_batch_topk": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "rkn_batch_autotune": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     "rkn_scan_windows_topk": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, _P, _P, _P]),
     "rkn_refine_setup": (C.c_int32, [_P, _P, C.c_int64, _P, _P, C.c_int32]),
     "rkn_residuals_fwd": (C.c_int32, [_P, _P, _P, _P]),
@@ -288,6 +289,15 @@ def rkn_trace(ctx, p: rkn_scan_params, seeds5, step_idx, states=None):
 
 def rkn_batch_plan(ctx, hp: rkn_hough_params, sp: rkn_scan_params) -> None:
     _check(ctx, load_library().rkn_batch_plan(ctx, C.byref(hp), C.byref(sp)))
+
+
+def rkn_batch_autotune(ctx, hp: rkn_hough_params, sp: rkn_scan_params, sample_events: int = 64, reps: int = 2):
+    """Plan the batch with the fastest block size; returns (block_steps, ms[3] for 4, 6, 8)."""
+    chosen = C.c_int32()
+    ms = (C.c_float * 3)()
+    _check(ctx, load_library().rkn_batch_autotune(ctx, C.byref(hp), C.byref(sp), int(sample_events), int(reps),
+                                                  C.byref(chosen), ms))
+    return chosen.value, list(ms)
 
 
 def rkn_batch_launch(ctx, best_index=None, best_score=None):

@@ -82,3 +82,43 @@ def test_batch_requires_plan_and_reupload_invalidates(rk, geo, ufield):
         rk.rkn_batch_launch(c.ctx, np.zeros(1, np.int64), np.zeros(1))
     assert e.value.status == rk.RKN_E_STATE
     c.close()
+
+
+def test_batch_block_sizes_agree_and_autotune(rk, geo, sfield):
+    """The cull is exact and the chords do not depend on the block grouping, so every
+    block size (and workgroup shape) gives the same scores up to the compiler's choice
+    of fused multiply-adds in each instantiation (far inside the oracle tolerance);
+    the autotuner leaves the batch planned with one of them."""
+    evs = synth.events_batch(geo, sfield, 10, seed=7, pool_size=20)
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    hp = rk.make_hough_params(b_ref=sfield.b_ref, max_cand=3, gran=(0.01, 100.0, 2.5, 2.5, 12.0),
+                              count=(3, 3, 3, 3, 3), grow=(1, 0, 1, 1, 0), count_max=5, max_seeds_window=600)
+    ne = len(evs)
+    ref = None
+    for b in (4, 6, 8):
+        rk.rkn_batch_plan(c.ctx, hp, rk.make_scan_params(n_steps=1000, precision=32, block_steps=b))
+        bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+        rk.rkn_batch_launch(c.ctx, bi, bs)
+        _, score, nin, _ = rk.rkn_batch_results(c.ctx, ne)
+        if ref is None:
+            ref = (score, nin, bi)
+        else:
+            d = float(np.max(np.abs(score - ref[0]) / np.maximum(np.abs(ref[0]), 1e-12)))
+            print(f"block_steps={b}: max rel score difference to block_steps=4: {d:.2e}", flush=True)
+            pu.check_scores(score, ref[0], rel=1e-5, abs_=1e-5)
+            pu.check_nin(nin, ref[1])
+            ev_seed = rk.rkn_batch_results(c.ctx, ne, want_scores=False)[3]
+            for e in range(ne):
+                if ev_seed[e + 1] > ev_seed[e]:
+                    pu.check_best(bi[e], ref[0][ev_seed[e]:ev_seed[e + 1]], offset=ev_seed[e])
+    chosen, ms = rk.rkn_batch_autotune(c.ctx, hp, rk.make_scan_params(n_steps=1000, precision=32),
+                                       sample_events=4, reps=1)
+    print(f"autotune: chose {chosen}, sample ms {ms}", flush=True)
+    assert chosen in (4, 6, 8) and np.isfinite(min(ms))
+    bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+    rk.rkn_batch_launch(c.ctx, bi, bs)
+    _, score, _, _ = rk.rkn_batch_results(c.ctx, ne)
+    pu.check_scores(score, ref[0], rel=1e-5, abs_=1e-5)
+    c.close()

@@ -143,24 +143,33 @@ def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind):
     c.close()
 
 
-def test_adjoint_gradient_matches_gpu_finite_differences(rk, geo, ufield):
+@pytest.mark.parametrize("kind", ["uniform", "solenoid"])
+def test_adjoint_gradient_matches_gpu_finite_differences(rk, geo, ufield, sfield, kind):
     """Self-consistency of the GPU pair: grad . v against a central difference of the
-    GPU's own Phi along v (a step that moves the residuals by ~0.05 mm)."""
-    c, evs, off, ev, s5, H = _setup(rk, geo, ufield, "uniform", per_event=2, seed=2)
-    n = ev.size
+    GPU's own Phi along v. Single-turn events, so that every hit has one closest
+    pass and Phi is smooth along v; the step moves the seed by ~0.01 mm (Phi's FP32
+    noise, ~2 sum|r| 1e-5 mm^2, stays ~1e-3 of the change)."""
+    field = ufield if kind == "uniform" else sfield
+    evs = [synth.event_single_turn(geo, field, s) for s in (1, 2, 3)]
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(field); c.upload_hits(off, wid, dr)
+    ev, s5 = _seeds(evs, 3, np.random.default_rng(2))
+    rk.rkn_refine_setup(c.ctx, rk.make_scan_params(n_steps=2000), ev, s5)
+    n, H = ev.size, int(np.diff(off).max())
     _forward(rk, c, n, H)
     g = np.zeros((n, 5))
     rk.rkn_adjoint_bwd(c.ctx, None, g, None, None)
     rng = np.random.default_rng(3)
     v = rng.standard_normal((n, 5)) / SCALE
-    v *= 0.05 / np.abs(v * np.array([500.0, 1.0, 500.0, 500.0, 500.0])).max(axis=1, keepdims=True)
+    v *= 0.01 / np.abs(v * np.array([500.0, 1.0, 500.0, 500.0, 500.0])).max(axis=1, keepdims=True)
     _, pp = _forward(rk, c, n, H, s5 + v)
     _, pm = _forward(rk, c, n, H, s5 - v)
     fd = (pp - pm) / 2.0
     an = (g * v).sum(axis=1)
-    err = np.abs(fd - an) / np.maximum(np.abs(an), 1e-3)
-    print(f"FD vs adjoint worst rel {err.max():.2e}", flush=True)
-    assert np.all(err < 5e-2), err
+    err = np.abs(fd - an) / np.maximum(np.abs(an), 1e-2)
+    print(f"{kind}: FD vs adjoint worst rel {err.max():.2e}", flush=True)
+    assert np.all(err < 2e-2), err
     c.close()
 
 
@@ -274,7 +283,7 @@ def test_autograd_function_matches_adjoint_entry_point(rk, geo, ufield):
     rk.rkn_adjoint_bwd(c.ctx, None, g, None, None)
     np.testing.assert_array_equal(r.detach().cpu().numpy(), resid)
     np.testing.assert_allclose(seeds.grad.cpu().numpy(), g, rtol=1e-12, atol=0)
-    assert float(loss) == pytest.approx(phi.sum(), rel=1e-6)
+    assert float(loss.detach()) == pytest.approx(phi.sum(), rel=1e-6)
     # stale backward
     r1 = ref.residuals(seeds)
     ref.residuals(seeds)

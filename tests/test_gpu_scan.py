@@ -128,7 +128,7 @@ def test_scan_solenoid_fp32(rk, ctx_s, orc_s, geo, sfield):
     pu.check_best(bi[0], osc)
 
 
-@pytest.mark.parametrize("block_steps", [4, 8])
+@pytest.mark.parametrize("block_steps", [4, 6, 8])
 def test_scan_block_steps_and_ragged_steps(rk, ctx_u, orc_u, ev1, block_steps):
     """n_steps not a multiple of the block; every block size gives the oracle's scores."""
     _note(f"scan block_steps={block_steps} n_steps=1999")
@@ -136,6 +136,23 @@ def test_scan_block_steps_and_ragged_steps(rk, ctx_u, orc_u, ev1, block_steps):
     score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_u, orc_u, [ev1], w, 1999, 32,
                                                          block_steps=block_steps)
     pu.check_scores(score, osc)
+    pu.check_best(bi[0], osc)
+
+
+@pytest.mark.parametrize("block_steps", [4, 6, 8])
+def test_scan_solenoid_workgroup_shapes(rk, ctx_s, orc_s, geo, sfield, block_steps):
+    """Field map, every workgroup shape (16, 12 and 8 waves): several tiles, a ragged
+    tile tail and a step count that no block size divides."""
+    _note(f"scan solenoid block_steps={block_steps} 1280+105 seeds, 1999 steps")
+    ev = synth.event_fixed_total(geo, sfield, 2, n_total=150, noise_frac=0.2)
+    t = ev.truth_seeds[0]
+    w = synth.make_windows([(0, 0, t, [0.03, 20, 3, 3, 3], [4, 4, 4, 4, 5]),
+                            (0, 1, t + np.array([0.01, 5, 0.5, -0.5, 0.3]), [0.01, 3, 0.5, 0.5, 0.5], [3, 1, 5, 1, 7])])
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_s, orc_s, [ev], w, 1999, 32,
+                                                         block_steps=block_steps)
+    rel = pu.check_scores(score, osc)
+    _note(f"  max rel score error {rel:.2e}")
+    pu.check_nin(nin, onin)
     pu.check_best(bi[0], osc)
 
 
@@ -247,7 +264,7 @@ def test_argument_errors(rk, geo, ufield, ev1):
     off, wid, dr = synth.pack_events([ev1])
     c.upload_hits(off, wid, dr)
     for bad in (dict(n_steps=0), dict(step_mm=-1.0), dict(precision=16), dict(lambda_mm2=float("nan")),
-                dict(block_steps=3)):
+                dict(block_steps=5)):
         with pytest.raises(rk.RknError) as e:
             rk.rkn_scan_windows(c.ctx, rk.make_scan_params(**bad), w, *out)
         assert e.value.status == rk.RKN_E_ARG
