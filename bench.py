@@ -191,7 +191,7 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
                 new_step[e, j] = 2.0 * w["half_width"][row] / 5.0
                 cur[e, j] = ns5[e, j]
                 cur_ok[e, j] = True
-        step = np.where(active[:, None], new_step, step)
+        step = np.where(active[:, None, None], new_step, step)
         rounds[ev_act] += 1
         ph = phi_on_gn_set(ns5[:, 0, :])
         done = active & (ph <= (1.0 + rtol) * phi_gn)
@@ -286,12 +286,15 @@ def main():
         log(f"cpu baseline: {cpu}")
         log(f"work counts: {work}")
     roof = None
+    bsteps = args.block_steps or 6
+    bwaves = {4: 16, 6: 12, 8: 8}[bsteps]
     if work is not None:
         f_alg = flops.per_seed_step("rz", work["cull_per_step"], work["pairs_per_step"])
         achieved = f_alg * seed_steps / (np.mean(ms_s) * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=round(achieved, 3), peak=flops.PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / flops.PEAK_FP32_TFLOPS, 4), traffic=None,
-                    flops_per_seed_step=round(f_alg, 2), kernel="scan_kernel<float, rz field, B=8>")
+                    flops_per_seed_step=round(f_alg, 2),
+                    kernel=f"scan_kernel<float, rz field, {bsteps}-step blocks, {bwaves} waves>")
     out = {
         "metric": METRIC, "value": value, "unit": "seed-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,

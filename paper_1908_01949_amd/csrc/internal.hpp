@@ -165,12 +165,12 @@ struct rkn_ctx {
   int r_ckpt = 64, r_nckpt = 0;
   rkn::DevBuf r_seeds, r_seeds0, r_trials, r_event, r_tiles, r_tiles6, r_ident, r_base6, r_mask, r_resid,
       r_argmin, r_resid6, r_argmin6, r_phi, r_phi6, r_phicur, r_tape, r_segbuf, r_list, r_grad, r_jtj, r_cgrad,
-      r_slab, r_counter;
+      r_slab, r_counter, r_tape6, r_segoff, r_segout, r_accept;
 
-  rkn::DevBuf* refine_buffers_[24] = {&r_seeds, &r_seeds0, &r_trials, &r_event,  &r_tiles,  &r_tiles6,
-                                      &r_ident, &r_base6,  &r_mask,   &r_resid,  &r_argmin, &r_resid6,
-                                      &r_argmin6, &r_phi,  &r_phi6,   &r_phicur, &r_tape,   &r_segbuf,
-                                      &r_list,  &r_grad,   &r_jtj,    &r_cgrad,  &r_slab,   &r_counter};
+  rkn::DevBuf* refine_buffers_[28] = {&r_seeds,  &r_seeds0, &r_trials, &r_event,  &r_tiles,  &r_tiles6, &r_ident,
+                                      &r_base6,  &r_mask,   &r_resid,  &r_argmin, &r_resid6, &r_argmin6, &r_phi,
+                                      &r_phi6,   &r_phicur, &r_tape,   &r_segbuf, &r_list,   &r_grad,   &r_jtj,
+                                      &r_cgrad,  &r_slab,   &r_counter, &r_tape6, &r_segoff, &r_segout, &r_accept};
   void refine_release() {
     for (rkn::DevBuf* b : refine_buffers_) b->release();
     r_ready = false;

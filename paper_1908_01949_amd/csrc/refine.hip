@@ -204,29 +204,6 @@ __device__ __forceinline__ float seg_wire_closest(const float p0[3], const float
   return w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
 }
 
-struct BwdArgs {
-  FieldDev field;
-  int64_t n;                  // seeds (slots)
-  int n_steps, ckpt, n_ckpt;
-  float h;
-  double R0, charge;
-  const double* seeds5;       // [n][5]
-  const int32_t* seed_event;  // [n]
-  const int32_t* ev_off;
-  const int32_t* hits_wire;   // wire id per hit, original order
-  const HitRec<float>* wire32;
-  const float* tape;          // [n_ckpt][13][n]
-  const float* resid;         // [n][max_hits]
-  const int32_t* argmin;      // [n][max_hits]
-  const float* cgrad;         // [n][max_hits] upstream dF/dr, or NULL: c = 2 r
-  int max_hits;
-  float* segbuf;              // [ckpt+1][13][n]
-  int2* list;                 // [max_hits][n]
-  int want_S;
-  double* grad;               // [n][5]
-  double* jtj;                // [n][25] or NULL
-};
-
 __device__ __forceinline__ State<float> load_state(const float* base, int64_t stride) {
   State<float> s;
   s.x = base[0 * stride];
@@ -245,137 +222,277 @@ __device__ __forceinline__ State<float> load_state(const float* base, int64_t st
   return s;
 }
 
-__device__ __forceinline__ void store_state(float* base, int64_t stride, const State<float>& s) {
-  base[0 * stride] = s.x;
-  base[1 * stride] = s.y;
-  base[2 * stride] = s.z;
-  base[3 * stride] = s.cx;
-  base[4 * stride] = s.cy;
-  base[5 * stride] = s.cz;
-  base[6 * stride] = s.tx;
-  base[7 * stride] = s.ty;
-  base[8 * stride] = s.tz;
-  base[9 * stride] = s.ctx;
-  base[10 * stride] = s.cty;
-  base[11 * stride] = s.ctz;
-  base[12 * stride] = s.lam;
+struct BwdArgs {
+  FieldDev field;
+  int64_t n;                  // seeds (slots)
+  int n_steps, ckpt, n_ckpt;
+  float h;
+  double R0, charge;
+  const double* seeds5;       // [n][5]
+  const int32_t* seed_event;  // [n]
+  const int32_t* ev_off;
+  const int32_t* hits_wire;   // wire id per hit, original order
+  const HitRec<float>* wire32;
+  const float* tape;          // [n_ckpt][13][n] checkpoints
+  const float* resid;         // [n][max_hits]
+  const int32_t* argmin;      // [n][max_hits] chord index, -1 outside the inlier set
+  const float* cgrad;         // [n][max_hits] upstream dF/dr, or NULL: c = 2 r
+  int max_hits;
+  float* segbuf;              // [n_ckpt][ckpt+1][6][n] recomputed (x, T) per step
+  int32_t* segoff;            // [n_ckpt+1][n] list offsets of each segment's hits
+  int2* list;                 // [max_hits][n] (chord, hit) grouped by segment
+  double* segout;             // [n_ckpt][kSegVals][n] per segment: Phi, a, A
+  double* grad;               // [n][5]
+  double* jtj;                // [n][25] or NULL
+};
+
+// Per segment: the transfer matrix Phi (7x7, row-major), the accumulated adjoint
+// source a (7) and the Gauss-Newton source A (7x7 symmetric, 28 upper entries).
+constexpr int kSegVals = 49 + 7 + 28;
+
+__device__ __forceinline__ int upper_index(int r, int c) {   // r <= c
+  return r * 7 - r * (r - 1) / 2 + (c - r);
 }
 
-template <int FIELD>
-__global__ void __launch_bounds__(64) adjoint_bwd_kernel(BwdArgs a) {
+// Group each seed's inlier hits by the segment of their minimising chord (counting
+// sort over segments; the order within a segment does not matter).
+__global__ void __launch_bounds__(64) adj_prep_kernel(BwdArgs a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.n) return;
-  const int e = a.seed_event[p];
-  const int hb = a.ev_off[e], nh = a.ev_off[e + 1] - hb;
   const int64_t n = a.n;
-  // inlier hits with their chord, sorted by chord index descending (insertion sort)
-  int cnt = 0;
+  const int e = a.seed_event[p];
+  const int nh = a.ev_off[e + 1] - a.ev_off[e];
+  for (int k = 0; k <= a.n_ckpt; ++k) a.segoff[(size_t)k * n + p] = 0;
+  for (int o = 0; o < nh; ++o) {
+    const int st = a.argmin[p * a.max_hits + o];
+    if (st >= 0) a.segoff[(size_t)(st / a.ckpt + 1) * n + p] += 1;
+  }
+  int acc = 0;
+  for (int k = 0; k <= a.n_ckpt; ++k) {
+    acc += a.segoff[(size_t)k * n + p];
+    a.segoff[(size_t)k * n + p] = acc;     // segoff[k] = first list slot of segment k
+  }
   for (int o = 0; o < nh; ++o) {
     const int st = a.argmin[p * a.max_hits + o];
     if (st < 0) continue;
-    int k = cnt++;
-    while (k > 0) {
-      const int2 prev = a.list[(size_t)(k - 1) * n + p];
-      if (prev.x >= st) break;
-      a.list[(size_t)k * n + p] = prev;
-      --k;
-    }
-    a.list[(size_t)k * n + p] = make_int2(st, o);
+    const size_t cs = (size_t)(st / a.ckpt) * n + p;
+    const int pos = a.segoff[cs];
+    a.segoff[cs] = pos + 1;
+    a.list[(size_t)pos * n + p] = make_int2(st, o);
   }
-  double lam[7] = {0, 0, 0, 0, 0, 0, 0};
-  double S[7][7];
+  // the scatter advanced each offset to the next segment's start: shift back
+  for (int k = a.n_ckpt; k >= 1; --k) a.segoff[(size_t)k * n + p] = a.segoff[(size_t)(k - 1) * n + p];
+  a.segoff[p] = 0;
+}
+
+// One (segment, seed) work item: recompute the segment's states from its checkpoint,
+// then walk its steps backwards from lambda = 0, S = 0 at the segment end:
+//   Phi <- M_n^T Phi,  a <- M_n^T a + sum c e,  A <- M_n^T A M_n + sum e e^T,
+// so that lambda(start) = Phi lambda(end) + a and S(start) = Phi S(end) Phi^T + A.
+template <int FIELD, bool WANT_S>
+__global__ void __launch_bounds__(64) adj_seg_kernel(BwdArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = a.n;
+  if (idx >= n * a.n_ckpt) return;
+  const int k = (int)(idx / n);
+  const int64_t p = idx - (int64_t)k * n;
+  const int n0 = k * a.ckpt;
+  const int n1 = min(n0 + a.ckpt, a.n_steps);
+  float* sb = a.segbuf + (size_t)k * (a.ckpt + 1) * 6 * n + p;
+  State<float> s = load_state(a.tape + (size_t)k * 13 * n + p, n);
+  const float lam = s.lam;
+  auto put = [&](int j, const State<float>& q) {
+    float* b = sb + (size_t)j * 6 * n;
+    b[0] = q.x;
+    b[n] = q.y;
+    b[2 * n] = q.z;
+    b[3 * n] = q.tx;
+    b[4 * n] = q.ty;
+    b[5 * n] = q.tz;
+  };
+  auto get = [&](int j) {
+    const float* b = sb + (size_t)j * 6 * n;
+    State<float> q{};
+    q.x = b[0];
+    q.y = b[n];
+    q.z = b[2 * n];
+    q.tx = b[3 * n];
+    q.ty = b[4 * n];
+    q.tz = b[5 * n];
+    q.lam = lam;
+    return q;
+  };
+  put(0, s);
+  for (int j = 1; j <= n1 - n0; ++j) {
+    rkn_step<float, FIELD>(s, a.field, a.field.nodes, a.h);
+    put(j, s);
+  }
+  const int e = a.seed_event[p];
+  const int hb = a.ev_off[e];
+  const int l0 = a.segoff[(size_t)k * n + p], l1 = a.segoff[(size_t)(k + 1) * n + p];
+  double Phi[7][7], av[7], A[28];
 #pragma unroll
-  for (int i = 0; i < 7; ++i)
+  for (int r = 0; r < 7; ++r) {
+    av[r] = 0.0;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) S[i][j] = 0.0;
-  int li = 0;
-  int2 cur = cnt > 0 ? a.list[p] : make_int2(-1, 0);
-  for (int k = a.n_ckpt - 1; k >= 0; --k) {
-    const int n0 = k * a.ckpt;
-    const int n1 = min(n0 + a.ckpt, a.n_steps);
-    // recompute the segment's states from its checkpoint
-    State<float> s = load_state(a.tape + (size_t)k * 13 * n + p, n);
-    store_state(a.segbuf + p, n, s);
-    for (int j = 1; j <= n1 - n0; ++j) {
-      rkn_step<float, FIELD>(s, a.field, a.field.nodes, a.h);
-      store_state(a.segbuf + (size_t)j * 13 * n + p, n, s);
-    }
-    for (int st = n1 - 1; st >= n0; --st) {
-      const State<float> sn = load_state(a.segbuf + (size_t)(st - n0) * 13 * n + p, n);
-      float M[7][7];
-      step_jacobian<FIELD>(sn, a.field, a.h, M);
-      // lambda <- M^T lambda ; S <- M^T S M
-      double nl[7];
+    for (int c = 0; c < 7; ++c) Phi[r][c] = r == c ? 1.0 : 0.0;
+  }
 #pragma unroll
-      for (int c = 0; c < 7; ++c) {
+  for (int q = 0; q < 28; ++q) A[q] = 0.0;
+  for (int st = n1 - 1; st >= n0; --st) {
+    const State<float> sn = get(st - n0);
+    float M[7][7];
+    step_jacobian<FIELD>(sn, a.field, a.h, M);
+    // Phi <- M^T Phi, a <- M^T a (column by column, in place)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      double col[7];
+#pragma unroll
+      for (int r = 0; r < 7; ++r) {
         double acc = 0.0;
 #pragma unroll
-        for (int r = 0; r < 7; ++r) acc += (double)M[r][c] * lam[r];
-        nl[c] = acc;
+        for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * Phi[q][c];
+        col[r] = acc;
       }
 #pragma unroll
-      for (int c = 0; c < 7; ++c) lam[c] = nl[c];
-      if (a.want_S) {
-        double SM[7][7];
+      for (int r = 0; r < 7; ++r) Phi[r][c] = col[r];
+    }
+    {
+      double col[7];
 #pragma unroll
-        for (int r = 0; r < 7; ++r)
+      for (int r = 0; r < 7; ++r) {
+        double acc = 0.0;
 #pragma unroll
-          for (int c = 0; c < 7; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int q = 0; q < 7; ++q) acc += S[r][q] * (double)M[q][c];
-            SM[r][c] = acc;
-          }
-#pragma unroll
-        for (int r = 0; r < 7; ++r)
-#pragma unroll
-          for (int c = r; c < 7; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * SM[q][c];
-            S[r][c] = acc;
-            S[c][r] = acc;
-          }
+        for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * av[q];
+        col[r] = acc;
       }
-      // contributions of the hits whose minimum is on chord st
-      while (li < cnt && cur.x == st) {
-        const int o = cur.y;
-        const State<float> sn1 = load_state(a.segbuf + (size_t)(st - n0 + 1) * 13 * n + p, n);
-        const HitRec<float> w = a.wire32[a.hits_wire[hb + o]];
-        const float p0[3] = {sn.x, sn.y, sn.z}, p1[3] = {sn1.x, sn1.y, sn1.z};
-        const float m[3] = {w.mx, w.my, w.mz}, u[3] = {w.ux, w.uy, w.uz};
-        float sstar, v[3];
-        const float d2 = seg_wire_closest(p0, p1, m, u, w.L, sstar, v);
-        const float D = sqrtf(d2);
-        if (D > 0.0f) {
-          const float iv = 1.0f / D;
-          double ev[7];
-          const float aa[3] = {(1.0f - sstar) * v[0] * iv, (1.0f - sstar) * v[1] * iv, (1.0f - sstar) * v[2] * iv};
-          const float bb[3] = {sstar * v[0] * iv, sstar * v[1] * iv, sstar * v[2] * iv};
 #pragma unroll
-          for (int c = 0; c < 7; ++c) {
-            double acc = c < 3 ? (double)aa[c] : 0.0;
+      for (int r = 0; r < 7; ++r) av[r] = col[r];
+    }
+    if constexpr (WANT_S) {
+      // A <- M^T A M over the upper triangle: B = A M by columns, then (M^T B)
+      double nA[28];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) acc += (double)M[q][c] * (double)bb[q];
-            ev[c] = acc;
-          }
-          const float r = a.resid[p * a.max_hits + o];
-          const double cg = a.cgrad ? (double)a.cgrad[p * a.max_hits + o] : 2.0 * (double)r;
+      for (int c = 0; c < 7; ++c) {
+        double b[7];
 #pragma unroll
-          for (int c = 0; c < 7; ++c) lam[c] += cg * ev[c];
-          if (a.want_S) {
+        for (int r = 0; r < 7; ++r) {
+          double acc = 0.0;
 #pragma unroll
-            for (int r2 = 0; r2 < 7; ++r2)
-#pragma unroll
-              for (int c = 0; c < 7; ++c) S[r2][c] += ev[r2] * ev[c];
-          }
+          for (int q = 0; q < 7; ++q) acc += A[r <= q ? upper_index(r, q) : upper_index(q, r)] * (double)M[q][c];
+          b[r] = acc;
         }
-        ++li;
-        cur = li < cnt ? a.list[(size_t)li * n + p] : make_int2(-1, 0);
+#pragma unroll
+        for (int r = 0; r <= c; ++r) {
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * b[q];
+          nA[upper_index(r, c)] = acc;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 28; ++q) A[q] = nA[q];
+    }
+    // sources of the hits whose minimum lies on chord st
+    for (int li = l0; li < l1; ++li) {
+      const int2 it = a.list[(size_t)li * n + p];
+      if (it.x != st) continue;
+      const int o = it.y;
+      const State<float> sn1 = get(st - n0 + 1);
+      const HitRec<float> w = a.wire32[a.hits_wire[hb + o]];
+      const float p0[3] = {sn.x, sn.y, sn.z}, p1[3] = {sn1.x, sn1.y, sn1.z};
+      const float m[3] = {w.mx, w.my, w.mz}, u[3] = {w.ux, w.uy, w.uz};
+      float sstar, v[3];
+      const float d2 = seg_wire_closest(p0, p1, m, u, w.L, sstar, v);
+      const float D = sqrtf(d2);
+      if (!(D > 0.0f)) continue;   // D = 0: the derivative is taken as 0
+      const float iv = 1.0f / D;
+      const float aa[3] = {(1.0f - sstar) * v[0] * iv, (1.0f - sstar) * v[1] * iv, (1.0f - sstar) * v[2] * iv};
+      const float bb[3] = {sstar * v[0] * iv, sstar * v[1] * iv, sstar * v[2] * iv};
+      double ev[7];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) {
+        double acc = c < 3 ? (double)aa[c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc += (double)M[q][c] * (double)bb[q];
+        ev[c] = acc;
+      }
+      const float r = a.resid[p * a.max_hits + o];
+      const double cg = a.cgrad ? (double)a.cgrad[p * a.max_hits + o] : 2.0 * (double)r;
+#pragma unroll
+      for (int c = 0; c < 7; ++c) av[c] += cg * ev[c];
+      if constexpr (WANT_S) {
+#pragma unroll
+        for (int r2 = 0; r2 < 7; ++r2)
+#pragma unroll
+          for (int c = r2; c < 7; ++c) A[upper_index(r2, c)] += ev[r2] * ev[c];
       }
     }
   }
-  // P = dy0/ds (7 x 5) from the FP64 seed
+  double* out = a.segout + (size_t)k * kSegVals * n + p;
+#pragma unroll
+  for (int r = 0; r < 7; ++r)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) out[(size_t)(r * 7 + c) * n] = Phi[r][c];
+#pragma unroll
+  for (int r = 0; r < 7; ++r) out[(size_t)(49 + r) * n] = av[r];
+  if constexpr (WANT_S) {
+#pragma unroll
+    for (int q = 0; q < 28; ++q) out[(size_t)(56 + q) * n] = A[q];
+  }
+}
+
+// Per seed: lambda_0 and S_0 from the segments, last to first, then the seed
+// derivatives through P = dy0/dseed: grad = P^T lambda_0, J^T J = P^T S_0 P.
+template <bool WANT_S>
+__global__ void __launch_bounds__(64) adj_combine_kernel(BwdArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  const int64_t n = a.n;
+  double lam[7] = {0, 0, 0, 0, 0, 0, 0};
+  double S[28];
+#pragma unroll
+  for (int q = 0; q < 28; ++q) S[q] = 0.0;
+  for (int k = a.n_ckpt - 1; k >= 0; --k) {
+    const double* in = a.segout + (size_t)k * kSegVals * n + p;
+    double Phi[7][7];
+#pragma unroll
+    for (int r = 0; r < 7; ++r)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) Phi[r][c] = in[(size_t)(r * 7 + c) * n];
+    double nl[7];
+#pragma unroll
+    for (int r = 0; r < 7; ++r) {
+      double acc = in[(size_t)(49 + r) * n];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) acc += Phi[r][c] * lam[c];
+      nl[r] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < 7; ++r) lam[r] = nl[r];
+    if constexpr (WANT_S) {
+      // S <- Phi S Phi^T + A
+      double B[7][7];   // B = Phi S
+#pragma unroll
+      for (int r = 0; r < 7; ++r)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < 7; ++q) acc += Phi[r][q] * S[q <= c ? upper_index(q, c) : upper_index(c, q)];
+          B[r][c] = acc;
+        }
+#pragma unroll
+      for (int r = 0; r < 7; ++r)
+#pragma unroll
+        for (int c = r; c < 7; ++c) {
+          double acc = in[(size_t)(56 + upper_index(r, c)) * n];
+#pragma unroll
+          for (int q = 0; q < 7; ++q) acc += B[r][q] * Phi[c][q];
+          S[upper_index(r, c)] = acc;
+        }
+    }
+  }
   const double* sd = a.seeds5 + 5 * p;
   const double pm = sqrt(sd[2] * sd[2] + sd[3] * sd[3] + sd[4] * sd[4]);
   double P[7][5];
@@ -400,21 +517,23 @@ __global__ void __launch_bounds__(64) adjoint_bwd_kernel(BwdArgs a) {
     for (int i = 0; i < 7; ++i) acc += P[i][j] * lam[i];
     a.grad[p * 5 + j] = acc;
   }
-  if (a.jtj) {
+  if constexpr (WANT_S) {
+    if (a.jtj) {
 #pragma unroll
-    for (int r = 0; r < 5; ++r)
+      for (int r = 0; r < 5; ++r)
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        double acc = 0.0;
+        for (int c = 0; c < 5; ++c) {
+          double acc = 0.0;
 #pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          double sp = 0.0;
+          for (int i = 0; i < 7; ++i) {
+            double sp = 0.0;
 #pragma unroll
-          for (int j = 0; j < 7; ++j) sp += S[i][j] * P[j][c];
-          acc += P[i][r] * sp;
+            for (int j = 0; j < 7; ++j) sp += S[i <= j ? upper_index(i, j) : upper_index(j, i)] * P[j][c];
+            acc += P[i][r] * sp;
+          }
+          a.jtj[p * 25 + r * 5 + c] = acc;
         }
-        a.jtj[p * 25 + r * 5 + c] = acc;
-      }
+    }
   }
 }
 
@@ -470,19 +589,32 @@ __global__ void gn_solve_kernel(int64_t n, const double* __restrict__ jtj, const
   for (int k = 0; k < 6; ++k) {
     const double alpha = ldexp(1.0, -k);
     for (int d = 0; d < 5; ++d)
-      trials[((size_t)k * n + p) * 5 + d] = seeds[p * 5 + d] + (ok ? alpha * x[d] * sc[d] : 0.0);
+      trials[((size_t)p * 6 + k) * 5 + d] = seeds[p * 5 + d] + (ok ? alpha * x[d] * sc[d] : 0.0);
   }
 }
 
-__global__ void gn_accept_kernel(int64_t n, const double* __restrict__ trials, const double* __restrict__ phi_trial,
-                                 double* __restrict__ seeds, double* __restrict__ phi_cur) {
+// Take the first trial (alpha = 1, 1/2, ...) that lowers Phi; its forward outputs
+// (checkpoints, residuals, argmin chords) become the current ones, so the next
+// iteration's adjoint needs no forward pass of its own.
+__global__ void gn_accept_kernel(int64_t n, int n_ckpt, int max_hits, const double* __restrict__ trials,
+                                 const double* __restrict__ phi_trial, const float* __restrict__ tape6,
+                                 const float* __restrict__ resid6, const int32_t* __restrict__ argmin6,
+                                 double* __restrict__ seeds, double* __restrict__ phi_cur, float* __restrict__ tape,
+                                 float* __restrict__ resid, int32_t* __restrict__ argmin) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   for (int k = 0; k < 6; ++k) {
-    const double ph = phi_trial[(size_t)k * n + p];
+    const int64_t g = p * 6 + k;   // trials of a seed are adjacent
+    const double ph = phi_trial[g];
     if (ph < phi_cur[p]) {
       phi_cur[p] = ph;
-      for (int d = 0; d < 5; ++d) seeds[p * 5 + d] = trials[((size_t)k * n + p) * 5 + d];
+      for (int d = 0; d < 5; ++d) seeds[p * 5 + d] = trials[g * 5 + d];
+      for (int c = 0; c < n_ckpt; ++c)
+        for (int q = 0; q < 13; ++q) tape[((size_t)c * 13 + q) * n + p] = tape6[((size_t)c * 13 + q) * 6 * n + g];
+      for (int o = 0; o < max_hits; ++o) {
+        resid[p * max_hits + o] = resid6[g * max_hits + o];
+        argmin[p * max_hits + o] = argmin6[g * max_hits + o];
+      }
       break;
     }
   }
@@ -505,26 +637,23 @@ rkn_status rerr(rkn_ctx* c, hipError_t e, const char* where) {
   return e == hipErrorOutOfMemory ? RKN_E_NOMEM : RKN_E_DEVICE;
 }
 
-// Tiles over runs of equal events of a slot list (slots grouped by event), `copies`
-// times, copy k covering slots k*n .. k*n+n-1.
-std::vector<Tile> slot_tiles(const std::vector<int32_t>& ev, int copies, int T) {
+// Tiles over runs of equal events of a slot list (slots grouped by event).
+std::vector<Tile> slot_tiles(const std::vector<int32_t>& ev, int T) {
   std::vector<Tile> tiles;
   const int64_t n = (int64_t)ev.size();
-  for (int k = 0; k < copies; ++k) {
-    for (int64_t i = 0; i < n;) {
-      int64_t j = i;
-      while (j < n && ev[j] == ev[i]) ++j;
-      for (int64_t s = i; s < j; s += T) {
-        Tile t{};
-        t.window = 0;
-        t.event = ev[i];
-        t.n = (int32_t)std::min<int64_t>(T, j - s);
-        t.start = k * n + s;
-        t.gbase = k * n + s;
-        tiles.push_back(t);
-      }
-      i = j;
+  for (int64_t i = 0; i < n;) {
+    int64_t j = i;
+    while (j < n && ev[j] == ev[i]) ++j;
+    for (int64_t s = i; s < j; s += T) {
+      Tile t{};
+      t.window = 0;
+      t.event = ev[i];
+      t.n = (int32_t)std::min<int64_t>(T, j - s);
+      t.start = s;
+      t.gbase = s;
+      tiles.push_back(t);
     }
+    i = j;
   }
   return tiles;
 }
@@ -541,7 +670,8 @@ hipError_t refine_forward(rkn_ctx* c, bool trials, int define_mask, bool tape) {
                            trials ? c->r_resid6.as<float>() : c->r_resid.as<float>(),
                            trials ? c->r_argmin6.as<int32_t>() : c->r_argmin.as<int32_t>(),
                            trials ? c->r_phi6.as<double>() : c->r_phi.as<double>(),
-                           tape ? c->r_tape.as<float>() : nullptr, c->r_ckpt, c->r_nckpt, npos);
+                           tape ? (trials ? c->r_tape6.as<float>() : c->r_tape.as<float>()) : nullptr, c->r_ckpt,
+                           c->r_nckpt, npos);
 }
 
 hipError_t refine_backward(rkn_ctx* c, const float* cgrad, bool want_S) {
@@ -565,15 +695,28 @@ hipError_t refine_backward(rkn_ctx* c, const float* cgrad, bool want_S) {
   b.cgrad = cgrad;
   b.max_hits = c->max_hits_event > 0 ? c->max_hits_event : 1;
   b.segbuf = c->r_segbuf.as<float>();
+  b.segoff = c->r_segoff.as<int32_t>();
   b.list = c->r_list.as<int2>();
-  b.want_S = want_S ? 1 : 0;
+  b.segout = c->r_segout.as<double>();
   b.grad = c->r_grad.as<double>();
   b.jtj = want_S ? c->r_jtj.as<double>() : nullptr;
-  const dim3 grid((unsigned)((b.n + 63) / 64)), block(64);
-  if (c->field_kind == 0)
-    hipLaunchKernelGGL(adjoint_bwd_kernel<0>, grid, block, 0, c->stream, b);
-  else
-    hipLaunchKernelGGL(adjoint_bwd_kernel<1>, grid, block, 0, c->stream, b);
+  const dim3 blk(64);
+  const dim3 g1((unsigned)((b.n + 63) / 64));
+  const dim3 gs((unsigned)((b.n * b.n_ckpt + 63) / 64));
+  hipLaunchKernelGGL(adj_prep_kernel, g1, blk, 0, c->stream, b);
+  if (want_S) {
+    if (c->field_kind == 0)
+      hipLaunchKernelGGL((adj_seg_kernel<0, true>), gs, blk, 0, c->stream, b);
+    else
+      hipLaunchKernelGGL((adj_seg_kernel<1, true>), gs, blk, 0, c->stream, b);
+    hipLaunchKernelGGL(adj_combine_kernel<true>, g1, blk, 0, c->stream, b);
+  } else {
+    if (c->field_kind == 0)
+      hipLaunchKernelGGL((adj_seg_kernel<0, false>), gs, blk, 0, c->stream, b);
+    else
+      hipLaunchKernelGGL((adj_seg_kernel<1, false>), gs, blk, 0, c->stream, b);
+    hipLaunchKernelGGL(adj_combine_kernel<false>, g1, blk, 0, c->stream, b);
+  }
   return hipGetLastError();
 }
 
@@ -622,13 +765,17 @@ rkn_status rkn_refine_setup(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seed
   const int H = c->max_hits_event > 0 ? c->max_hits_event : 1;
   const int T = scan_tile(c, &c->r_params);
   std::vector<int32_t> ev(seed_event, seed_event + n_seeds);
-  std::vector<Tile> t1 = slot_tiles(ev, 1, T), t6 = slot_tiles(ev, 6, T);
+  // trials: the six step lengths of seed s at positions 6 s .. 6 s + 5, so that an
+  // event's trials share its tiles
+  std::vector<int32_t> ev6(6 * (size_t)n_seeds);
+  for (int64_t i = 0; i < 6 * n_seeds; ++i) ev6[i] = ev[i / 6];
+  std::vector<Tile> t1 = slot_tiles(ev, T), t6 = slot_tiles(ev6, T);
   c->r_ntiles = (int64_t)t1.size();
   c->r_ntiles6 = (int64_t)t6.size();
   std::vector<int64_t> ident(6 * n_seeds), base6(6 * n_seeds);
   for (int64_t i = 0; i < 6 * n_seeds; ++i) {
     ident[i] = i;
-    base6[i] = i % n_seeds;
+    base6[i] = i / 6;
   }
   const size_t n = (size_t)n_seeds;
   if ((e = c->r_seeds.ensure(sizeof(double) * 5 * n)) != hipSuccess ||
@@ -648,7 +795,10 @@ rkn_status rkn_refine_setup(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seed
       (e = c->r_phi6.ensure(sizeof(double) * 6 * n)) != hipSuccess ||
       (e = c->r_phicur.ensure(sizeof(double) * n)) != hipSuccess ||
       (e = c->r_tape.ensure(sizeof(float) * 13 * n * c->r_nckpt)) != hipSuccess ||
-      (e = c->r_segbuf.ensure(sizeof(float) * 13 * n * (ckpt_every + 1))) != hipSuccess ||
+      (e = c->r_tape6.ensure(sizeof(float) * 13 * 6 * n * c->r_nckpt)) != hipSuccess ||
+      (e = c->r_segbuf.ensure(sizeof(float) * 6 * n * (ckpt_every + 1) * c->r_nckpt)) != hipSuccess ||
+      (e = c->r_segoff.ensure(sizeof(int32_t) * n * (c->r_nckpt + 1))) != hipSuccess ||
+      (e = c->r_segout.ensure(sizeof(double) * kSegVals * n * c->r_nckpt)) != hipSuccess ||
       (e = c->r_list.ensure(sizeof(int2) * n * H)) != hipSuccess ||
       (e = c->r_grad.ensure(sizeof(double) * 5 * n)) != hipSuccess ||
       (e = c->r_jtj.ensure(sizeof(double) * 25 * n)) != hipSuccess ||
@@ -764,21 +914,23 @@ rkn_status rkn_gn_refine(rkn_ctx* c, int32_t iters, const double* scale, double*
   if (e == hipSuccess) e = refine_forward(c, false, 0, true);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->r_phicur.p, c->r_phi.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream);
+  const int H = c->max_hits_event > 0 ? c->max_hits_event : 1;
   for (int it = 0; it < iters && e == hipSuccess; ++it) {
     hipLaunchKernelGGL(copy_phi_kernel, g1, b1, 0, c->stream, n, c->r_phicur.as<double>(), phi_hist.as<double>(),
                        iters + 1, it);
-    if (it > 0) e = refine_forward(c, false, 0, true);
-    if (e == hipSuccess) e = refine_backward(c, nullptr, true);
+    e = refine_backward(c, nullptr, true);
     if (e == hipSuccess) {
       hipLaunchKernelGGL(gn_solve_kernel, g1, b1, 0, c->stream, n, c->r_jtj.as<double>(), c->r_grad.as<double>(),
                          c->r_seeds.as<double>(), scale[0], scale[1], scale[2], scale[3], scale[4],
                          c->r_trials.as<double>());
       e = hipGetLastError();
     }
-    if (e == hipSuccess) e = refine_forward(c, true, 0, false);
+    if (e == hipSuccess) e = refine_forward(c, true, 0, true);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(gn_accept_kernel, g1, b1, 0, c->stream, n, c->r_trials.as<double>(), c->r_phi6.as<double>(),
-                         c->r_seeds.as<double>(), c->r_phicur.as<double>());
+      hipLaunchKernelGGL(gn_accept_kernel, g1, b1, 0, c->stream, n, c->r_nckpt, H, c->r_trials.as<double>(),
+                         c->r_phi6.as<double>(), c->r_tape6.as<float>(), c->r_resid6.as<float>(),
+                         c->r_argmin6.as<int32_t>(), c->r_seeds.as<double>(), c->r_phicur.as<double>(),
+                         c->r_tape.as<float>(), c->r_resid.as<float>(), c->r_argmin.as<int32_t>());
       e = hipGetLastError();
     }
   }

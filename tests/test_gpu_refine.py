@@ -147,29 +147,38 @@ def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind):
 def test_adjoint_gradient_matches_gpu_finite_differences(rk, geo, ufield, sfield, kind):
     """Self-consistency of the GPU pair: grad . v against a central difference of the
     GPU's own Phi along v. Single-turn events, so that every hit has one closest
-    pass and Phi is smooth along v; the step moves the seed by ~0.01 mm (Phi's FP32
-    noise, ~2 sum|r| 1e-5 mm^2, stays ~1e-3 of the change)."""
+    pass and Phi is smooth along v; the step moves the seed by ~0.05 mm (Phi's FP32
+    noise enters through 2 sum|r| times the ~1e-4 mm FP32 residual noise)."""
     field = ufield if kind == "uniform" else sfield
     evs = [synth.event_single_turn(geo, field, s) for s in (1, 2, 3)]
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(field); c.upload_hits(off, wid, dr)
-    ev, s5 = _seeds(evs, 3, np.random.default_rng(2))
+    ev, s5 = _seeds(evs, 6, np.random.default_rng(2))
     rk.rkn_refine_setup(c.ctx, rk.make_scan_params(n_steps=2000), ev, s5)
     n, H = ev.size, int(np.diff(off).max())
-    _forward(rk, c, n, H)
+    resid, _ = _forward(rk, c, n, H)
     g = np.zeros((n, 5))
     rk.rkn_adjoint_bwd(c.ctx, None, g, None, None)
     rng = np.random.default_rng(3)
     v = rng.standard_normal((n, 5)) / SCALE
-    v *= 0.01 / np.abs(v * np.array([500.0, 1.0, 500.0, 500.0, 500.0])).max(axis=1, keepdims=True)
+    v *= 0.05 / np.abs(v * np.array([500.0, 1.0, 500.0, 500.0, 500.0])).max(axis=1, keepdims=True)
     _, pp = _forward(rk, c, n, H, s5 + v)
     _, pm = _forward(rk, c, n, H, s5 - v)
     fd = (pp - pm) / 2.0
     an = (g * v).sum(axis=1)
-    err = np.abs(fd - an) / np.maximum(np.abs(an), 1e-2)
-    print(f"{kind}: FD vs adjoint worst rel {err.max():.2e}", flush=True)
-    assert np.all(err < 2e-2), err
+    noise = 2.0 * np.nansum(np.abs(resid), axis=1) * 1e-4
+    tol = 2e-2 * np.abs(an) + noise
+    err = np.abs(fd - an)
+    # D = |closest-approach vector| is not differentiable at D = 0: keep the seeds whose
+    # inlier distances stay away from 0 along the whole difference stencil (which moves
+    # the trajectory by at most ~0.05 mm)
+    dmin = np.array([np.nanmin(resid[p, :evs[ev[p]].wire_id.size] + evs[ev[p]].drift) for p in range(n)])
+    ok = dmin > 0.15
+    print(f"{kind}: {ok.sum()} of {n} seeds with min D > 0.15 mm; FD vs adjoint worst err/tol "
+          f"{np.max((err / tol)[ok]):.2e}, worst rel {np.max((err / np.abs(an))[ok]):.2e}", flush=True)
+    assert ok.sum() >= n // 4
+    assert np.all(err[ok] < tol[ok]), (err, tol, dmin)
     c.close()
 
 
