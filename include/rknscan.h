@@ -266,7 +266,9 @@ rkn_status rkn_refine_setup(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_se
 /* Forward pass at seeds5 ([n][5]; NULL keeps the current seeds): resid [n][H]
  * (H = the largest hit count of an uploaded event; per row the event's hits in
  * upload order, NaN for hits outside the inlier set and for unused columns) and
- * phi [n]. Records the checkpoints used by rkn_adjoint_bwd. Either output may be NULL. */
+ * phi [n]. An inlier hit that no step block approaches within its drift +
+ * sqrt(lambda) + block_steps h / 2 + 0.05 mm (the pruning reach) gets +inf, and so
+ * does phi. Records the checkpoints used by rkn_adjoint_bwd. Either output may be NULL. */
 rkn_status rkn_residuals_fwd(rkn_ctx *ctx, const double *seeds5, float *resid, double *phi);
 
 /* Adjoint of the last forward pass. d_resid [n][H]: upstream gradient dF/dr (entries

@@ -307,9 +307,10 @@ double orc_score(const orc_geometry *g, const orc_field *f, const orc_params *p,
  * a hit is tested for a block only if its layer band, widened by the event's
  * largest drift + sqrt(lambda) + 1 mm, meets the block's radial range; the test
  * keeps the hit if the line of its wire passes within B h / 2 + sqrt(lambda) +
- * 1 mm + d of the block's middle point (every chord point lies within B h / 2 of
- * it); kept hits are compared with each chord of the block. cull counts the
- * tests, pairs the chord/hit distances evaluated.                              */
+ * 0.05 mm + d of the block's middle point (every chord point lies within B h / 2
+ * of it; the 0.05 mm covers the rounding of that test in FP32); kept hits are
+ * compared with each chord of the block. cull counts the tests, pairs the
+ * chord/hit distances evaluated.                                               */
 double orc_score_blocked(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
                          int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t B,
                          int32_t *n_in, int64_t *cull, int64_t *pairs) {
@@ -356,7 +357,7 @@ double orc_score_blocked(const orc_geometry *g, const orc_field *f, const orc_pa
       r0 = c[0] - m[0]; r1 = c[1] - m[1]; r2 = c[2] - m[2];
       t = r0 * u[0] + r1 * u[1] + r2 * u[2];
       dl2 = r0 * r0 + r1 * r1 + r2 * r2 - t * t;
-      thr = 0.5 * B * h + sl + 1.0 + (double)drift[i];
+      thr = 0.5 * B * h + sl + 0.05 + (double)drift[i];
       if (dl2 > thr * thr) continue;
       for (j = 0; j < nb; ++j) {
         double v = orc_seg_wire_dist2(pts[j], pts[j + 1], m, u, L);

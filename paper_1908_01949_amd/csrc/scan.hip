@@ -29,7 +29,8 @@ namespace rkn {
 
 constexpr int kCap = 256;          // work-list entries per wave
 constexpr int kTabBins = 1024;     // 1 mm radial bins, the last one open-ended
-constexpr float kBandMargin = 1.0f;
+constexpr float kBandMargin = 1.0f;   // radial band table
+constexpr float kCullMargin = 0.05f;  // sphere test: covers FP32 rounding of the test (~1e-2 mm)
 
 struct ScanArgs {
   FieldDev field;
@@ -158,16 +159,38 @@ __device__ __forceinline__ R load_coherent(const R* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Dense pass over a wave's work list: item = (lane << 16) | hit.
+// Fold one item's block minimum into the seed's running minimum for the hit. In
+// the scan, a block whose minimum is not below (d + sqrt(lambda))^2 cannot change
+// the hit's term (it stays lambda unless another block comes closer), so it is not
+// written. The refinement pass writes every block (its inlier set is fixed).
+template <typename R, int TILE, int MODE, typename S>
+__device__ __forceinline__ void fold_min(S* slab, int hh, int wave, int s, R d2, int chord, R lim2) {
+  if constexpr (MODE == 0) {
+    if (!(d2 < lim2)) return;
+    atomic_min_nonneg(slab + (size_t)hh * TILE + wave * 64 + s, d2);
+  } else {
+    // (distance bits, chord index): the minimum distance, then the lowest chord
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint((float)d2) << 32) | (unsigned long long)(unsigned)chord;
+    atomicMin(reinterpret_cast<unsigned long long*>(slab + (size_t)hh * TILE + wave * 64 + s), key);
+  }
+}
+
+// Dense pass over a wave's work list: item = (lane << 16) | hit. Full groups of 64
+// items take one item per lane and all chords of the block; the remaining n < 64
+// items take G lanes each (G = 8, 4 or 2 with G n <= 64), the chords of an item
+// strided over its lanes and their minimum (distance, then chord) reduced across
+// the G lanes, so the tail pass costs about B / G chords instead of B.
 template <typename R, int B, int TILE, int MODE, typename S>
 __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, const R* pts,
                                             const HitRec<R>* s_hits, S* slab, int wave, int lane,
-                                            int nb, int step0) {
+                                            int nb, int step0, R sqrt_lam) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int i = lane; i < n_items; i += 64) {
-    const uint32_t it = items[i];
+  int done = 0;
+  for (; n_items - done >= 64; done += 64) {
+    const uint32_t it = items[done + lane];
     const int s = (int)(it >> 16), hh = (int)(it & 0xffffu);
     const HitRec<R> w = s_hits[hh];
     R px = pts[0 * 64 + s], py = pts[1 * 64 + s], pz = pts[2 * 64 + s];
@@ -188,13 +211,39 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
         pz = qz;
       }
     }
-    if constexpr (MODE == 0) {
-      atomic_min_nonneg(slab + (size_t)hh * TILE + wave * 64 + s, dmin);
-    } else {
-      // (distance bits, chord index): the minimum distance, then the lowest chord
-      const unsigned long long key = ((unsigned long long)__float_as_uint((float)dmin) << 32) |
-                                     (unsigned long long)(unsigned)(step0 + jmin);
-      atomicMin(reinterpret_cast<unsigned long long*>(slab + (size_t)hh * TILE + wave * 64 + s), key);
+    const R lim = w.drift + sqrt_lam;
+    fold_min<R, TILE, MODE>(slab, hh, wave, s, dmin, step0 + jmin, lim * lim);
+  }
+  const int n_rem = n_items - done;
+  if (n_rem > 0) {
+    const int G = n_rem <= 8 ? 8 : (n_rem <= 16 ? 4 : (n_rem <= 32 ? 2 : 1));
+    const int k = lane / G, sub = lane - k * G;
+    const bool act = k < n_rem;
+    const uint32_t it = items[done + (act ? k : 0)];
+    const int s = (int)(it >> 16), hh = (int)(it & 0xffffu);
+    const HitRec<R> w = s_hits[hh];
+    R dmin = (R)INFINITY;
+    int jmin = 0x7fffffff;
+    for (int j = sub; j < nb; j += G) {
+      const R d2 = seg_wire_d2<R>(pts[(j * 3 + 0) * 64 + s], pts[(j * 3 + 1) * 64 + s], pts[(j * 3 + 2) * 64 + s],
+                                  pts[(j * 3 + 3) * 64 + s], pts[(j * 3 + 4) * 64 + s], pts[(j * 3 + 5) * 64 + s],
+                                  w.mx, w.my, w.mz, w.ux, w.uy, w.uz, w.L);
+      if (d2 < dmin) {   // chords are visited in increasing order: keeps the lowest on ties
+        dmin = d2;
+        jmin = j;
+      }
+    }
+    for (int o = 1; o < G; o <<= 1) {
+      const R od = __shfl_xor(dmin, o, 64);
+      const int oj = __shfl_xor(jmin, o, 64);
+      if (od < dmin || (od == dmin && oj < jmin)) {
+        dmin = od;
+        jmin = oj;
+      }
+    }
+    if (act && sub == 0) {
+      const R lim = w.drift + sqrt_lam;
+      fold_min<R, TILE, MODE>(slab, hh, wave, s, dmin, step0 + jmin, lim * lim);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -302,7 +351,8 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     __syncthreads();
 
     const int nblocks = (a.n_steps + B - 1) / B;
-    const R Kcull = (R)(0.5 * B * a.h + sqrt(lam) + (double)kBandMargin);
+    const R Kcull = (R)(0.5 * B * a.h + sqrt(lam) + (double)kCullMargin);
+    const R sqrt_lam = (R)sqrt(lam);
     for (int blk = 0; blk < nblocks; ++blk) {
       const int nb = min(B, a.n_steps - blk * B);
       const int jc = nb / 2;
@@ -362,12 +412,12 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
           n_items += (int)__popcll(m);
           if (n_items > kCap - 64) {
-            flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B);
+            flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B, sqrt_lam);
             n_items = 0;
           }
         }
       }
-      if (n_items) flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B);
+      if (n_items) flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B, sqrt_lam);
     }
     __threadfence();
 
@@ -381,7 +431,8 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         double ph = 0.0;
         for (int i = 0; i < nh; ++i) {
           const unsigned long long key = load_coherent(slab + (size_t)i * TILE + tid);
-          const float d2 = __uint_as_float((unsigned)(key >> 32));
+          // no block came within the cull reach: the distance is beyond it (+inf here)
+          const float d2 = key == 0xffffffffffffffffULL ? INFINITY : __uint_as_float((unsigned)(key >> 32));
           const double r = sqrt((double)d2) - (double)s_hits[i].drift;
           const int o = a.hits_orig[hbase + i];
           bool in;
@@ -392,7 +443,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
             in = valid && mrow[o] != 0;
           }
           rrow[o] = in ? (float)r : NAN;
-          arow[o] = in ? (int32_t)(unsigned)(key & 0xffffffffu) : -1;
+          arow[o] = (in && key != 0xffffffffffffffffULL) ? (int32_t)(unsigned)(key & 0xffffffffu) : -1;
           if (in) ph += r * r;
         }
         for (int i = nh; i < a.max_hits; ++i) {
