@@ -257,6 +257,8 @@ def main():
     lam = 64.0
     sp = rk.make_scan_params(n_steps=args.rkn_steps, precision=32, lambda_mm2=lam, block_steps=args.block_steps)
     hp = cfg4_hough_params(field)
+    bsteps, tile = rk.rkn_scan_shape(ctx.ctx, sp)
+    log(f"scan shape: {bsteps}-step blocks, {tile} seeds per tile ({tile // 64} waves)")
     rk.rkn_batch_plan(ctx.ctx, hp, sp)
     ne = args.events
     bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
@@ -286,8 +288,7 @@ def main():
         log(f"cpu baseline: {cpu}")
         log(f"work counts: {work}")
     roof = None
-    bsteps = args.block_steps or 6
-    bwaves = {4: 16, 6: 12, 8: 8}[bsteps]
+    bwaves = tile // 64
     if work is not None:
         f_alg = flops.per_seed_step("rz", work["cull_per_step"], work["pairs_per_step"])
         achieved = f_alg * seed_steps / (np.mean(ms_s) * 1e-3) / 1e12
@@ -303,7 +304,7 @@ def main():
                                f"65x129 (r,z) solenoid map, circle-Hough windows (1e3-1e5 seeds/event), "
                                f"{args.rkn_steps} RKN steps of 1 mm, FP64 scores and argmin",
                    "n_events": ne, "n_seeds": int(ns), "n_windows": int(nw), "rkn_steps": args.rkn_steps,
-                   "lambda_mm2": lam},
+                   "lambda_mm2": lam, "block_steps": bsteps, "seeds_per_tile": tile},
         "events_per_s": ne * args.steps / dt,
         "ms_hough": float(np.mean(ms_h)), "ms_scan": float(np.mean(ms_s)),
         "roofline": roof, "cpu_baseline": cpu,

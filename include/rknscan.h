@@ -175,6 +175,12 @@ rkn_status rkn_scan_windows(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_wi
                             const rkn_window *w, double *score, int32_t *n_in,
                             int64_t *best_index, double *best_score);
 
+/* The kernel shape a scan with these parameters uses on the current hits: RKN steps
+ * per cull block and seeds per tile (= lanes per workgroup), after the default and
+ * the LDS/occupancy fit are resolved (tiles of the batched path and of
+ * rkn_scan_windows are built for it). Either output may be NULL. */
+rkn_status rkn_scan_shape(rkn_ctx *ctx, const rkn_scan_params *p, int32_t *block_steps, int32_t *seeds_per_tile);
+
 /* The scan of rkn_scan_windows followed by the choice of the k (1..RKN_TOPK_MAX)
  * lowest-score seeds of every event, on the device: the step of the coarse-to-fine
  * refinement that keeps the best seeds of a scan before finer seed sets are built

@@ -418,6 +418,17 @@ static rkn_status prepare_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t 
   return RKN_OK;
 }
 
+rkn_status rkn_scan_shape(rkn_ctx* c, const rkn_scan_params* p, int32_t* block_steps, int32_t* seeds_per_tile) {
+  if (!c) return RKN_E_ARG;
+  rkn_status st = check_scan_params(c, p);
+  if (st != RKN_OK) return st;
+  if ((st = check_state(c)) != RKN_OK) return st;
+  RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
+  if (block_steps) *block_steps = p->precision == 64 ? 4 : rkn::resolve_block_steps(c, p);
+  if (seeds_per_tile) *seeds_per_tile = rkn::scan_tile(c, p);
+  return RKN_OK;
+}
+
 rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
                             double* score, int32_t* n_in, int64_t* best_index, double* best_score) {
   if (!c) return RKN_E_ARG;

@@ -23,6 +23,8 @@
 // d + sqrt(lambda), where the term is lambda whatever the distance is.
 #include <type_traits>
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace rkn {
@@ -559,15 +561,41 @@ int resolve_block_steps(const rkn_ctx* c, const rkn_scan_params* p) {
   return (p->precision == 32 && c->field_kind == 1) ? 6 : 8;
 }
 
+// Workgroups of a kernel that one CU holds, from the kernel's register and LDS
+// needs (code-object metadata) and the CU's resources on gfx950: 4 SIMDs of 512
+// VGPRs per lane (allocated in granules of 8) and at most 8 waves each, and the
+// LDS of the device. (This does not use the runtime's occupancy query, whose
+// answer for wide workgroups differs between HIP runtime versions.)
+static int resident_per_cu(const rkn_ctx* c, const void* kern, int threads, size_t smem) {
+  hipFuncAttributes at{};
+  if (hipFuncGetAttributes(&at, kern) != hipSuccess) return 0;
+  const int waves = (threads + 63) / 64;
+  const size_t lds = smem + at.sharedSizeBytes;
+  if (lds > (size_t)c->max_lds_block) return 0;
+  const int by_lds = lds > 0 ? (int)((size_t)c->max_lds_block / lds) : 32;
+  const int regs = at.numRegs > 0 ? ((at.numRegs + 7) / 8) * 8 : 8;
+  const int per_simd = std::min(512 / regs, 8);
+  const int by_regs = (4 * per_simd) / waves;
+  return std::min(by_lds, by_regs);
+}
+
+template <typename R, int FIELD, int B, int WAVES>
+static bool shape_fits(const rkn_ctx* c) {
+  const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
+  if (smem + 256 > (size_t)c->max_lds_block) return false;
+  return resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0>, 64 * WAVES, smem) >= 1;
+}
+
 // Waves per workgroup. The FP32 field-map path stages the map in LDS once per
-// workgroup, so it uses the widest workgroup whose LDS fits: 16 waves with 4-step
+// workgroup, so it uses the widest workgroup that fits: 16 waves with 4-step
 // blocks, 12 with 6-step blocks, 8 with 8-step blocks (falling back to 8 waves when
-// an event has too many hits for the wider shape).
+// an event has too many hits, or the runtime reserves too much LDS, for the wider
+// shape). Tiles are built for the shape chosen here, and the launch uses the same.
 static int scan_waves(const rkn_ctx* c, int precision, int B) {
   if (precision == 64 || c->field_kind == 0) return 4;
-  const int w = B == 4 ? 16 : B == 6 ? 12 : 8;
-  if (w > 8 && scan_lds_bytes(c, 4, 1, B, w) + 256 > (size_t)c->max_lds_block) return 8;
-  return w;
+  if (B == 4 && shape_fits<float, 1, 4, 16>(c)) return 16;
+  if (B == 6 && shape_fits<float, 1, 6, 12>(c)) return 12;
+  return 8;
 }
 
 template <typename R, int FIELD, int B, int WAVES, int MODE = 0>
@@ -582,9 +610,7 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   auto kern = scan_kernel<R, FIELD, B, WAVES, MODE>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TILE, smem);
-  if (e != hipSuccess) return e;
+  const int per_cu = resident_per_cu(c, (const void*)kern, TILE, smem);
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   int64_t grid = (int64_t)per_cu * c->n_cu;
   if (grid > max_tiles) grid = max_tiles;

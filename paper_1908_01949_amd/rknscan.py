@@ -84,6 +84,7 @@ _SIGS = {
     "rkn_batch_topk": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "rkn_batch_autotune": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     "rkn_scan_windows_topk": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, _P, _P, _P]),
+    "rkn_scan_shape": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_refine_setup": (C.c_int32, [_P, _P, C.c_int64, _P, _P, C.c_int32]),
     "rkn_residuals_fwd": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_adjoint_bwd": (C.c_int32, [_P, _P, _P, _P, _P]),
@@ -251,6 +252,13 @@ def rkn_scan_windows(ctx, p: rkn_scan_params, windows, score=None, n_in=None, be
     _check(ctx, load_library().rkn_scan_windows(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
                                                 _ptr(best_index), _ptr(best_score)))
     return score, n_in, best_index, best_score
+
+
+def rkn_scan_shape(ctx, p: rkn_scan_params):
+    """(block_steps, seeds_per_tile) the scan uses for these parameters on the current hits."""
+    b = C.c_int32(); t = C.c_int32()
+    _check(ctx, load_library().rkn_scan_shape(ctx, C.byref(p), C.byref(b), C.byref(t)))
+    return b.value, t.value
 
 
 def rkn_scan_windows_topk(ctx, p: rkn_scan_params, windows, k, index=None, score=None, seeds5=None,
