@@ -133,7 +133,7 @@ void rkn_destroy(rkn_ctx* c) {
                     &c->ev_tiles, &c->parts, &c->counter, &c->mscratch, &c->out_score, &c->out_nin,
                     &c->out_best_i, &c->out_best_e, &c->trace_buf, &c->seeds_buf, &c->perm_buf,
                     &c->wire_wx, &c->wire_wy, &c->hits_wire, &c->hough_acc, &c->hough_max,
-                    &c->hough_cand_n, &c->hough_cand, &c->hough_slots, &c->hough_nsel, &c->hits_orig,
+                    &c->hough_cand_n, &c->hough_cand, &c->hough_slots, &c->hough_nsel, &c->hits_orig, &c->hits_phi, &c->layer_ext,
                     &c->sel_seg, &c->sel_win, &c->sel_idx, &c->sel_sc, &c->sel_seed};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->extra) b.release();
@@ -283,6 +283,9 @@ rkn_status rkn_upload_hits(rkn_ctx* c, int32_t n_events, const int32_t* ev_off, 
   if (e == hipSuccess) e = c->layer_off.ensure(sizeof(int32_t) * (size_t)n_events * (c->n_layers + 1));
   if (e == hipSuccess) e = c->ev_maxdrift.ensure(sizeof(float) * (size_t)n_events);
   if (e == hipSuccess) e = c->hits_orig.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(H, 1));
+  if (e == hipSuccess) e = c->hits_phi.ensure(sizeof(float) * (size_t)std::max<int64_t>(H, 1));
+  if (e == hipSuccess)
+    e = c->layer_ext.ensure(sizeof(float) * (size_t)std::max(n_events, 1) * (size_t)std::max(c->n_layers, 1));
   if (e == hipSuccess) {
     c->n_events = n_events;
     e = rkn::launch_prep_hits(c, d_wid.as<int32_t>(), d_drift.as<float>());

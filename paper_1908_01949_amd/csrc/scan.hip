@@ -29,10 +29,12 @@
 
 namespace rkn {
 
-constexpr int kCap = 256;          // work-list entries per wave
+constexpr int kCap = 192;          // work-list entries per wave
 constexpr int kTabBins = 1024;     // 1 mm radial bins, the last one open-ended
 constexpr float kBandMargin = 1.0f;   // radial band table
 constexpr float kCullMargin = 0.05f;  // sphere test: covers FP32 rounding of the test (~1e-2 mm)
+constexpr int kSectors = 32;          // azimuthal sectors of the candidate table
+constexpr float kPi = 3.14159265358979f;
 
 struct ScanArgs {
   FieldDev field;
@@ -42,7 +44,10 @@ struct ScanArgs {
   const int32_t* layer_off;   // [n_events][n_layers+1]
   const float2* layer_r;      // (rmin, rmax) per layer
   const float* ev_maxdrift;
+  const float* hits_phi;      // azimuth of each layer-ordered hit's wire centre
+  const float* layer_ext;     // [n_events][n_layers] largest azimuth half-extent of a wire
   int n_layers;
+  int sect_bytes;             // LDS bytes reserved for the layer x sector table
   int hits_bytes;             // LDS bytes reserved for hit records
   int field_bytes;            // LDS bytes reserved for the field map (0: uniform)
   const Tile* tiles;
@@ -74,29 +79,47 @@ struct ScanArgs {
 };
 
 // ---------------------------------------------------------------------------------
-// Upload-time preparation: per event, order the hits by layer (stable), build the
-// FP32/FP64 hit records and the per-layer offsets, and the event's largest drift.
+// Upload-time preparation: per event, order the hits by layer and, within a layer,
+// by the azimuth of the wire centre (ties by upload order); build the FP32/FP64 hit
+// records, the per-layer offsets, the event's largest drift, each hit's azimuth and
+// per layer the largest azimuth half-extent of a wire over |t| <= L (a stereo wire
+// turns in azimuth along z; the extremes are at its ends).
 __global__ void __launch_bounds__(256)
 prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__ wire_id,
                  const float* __restrict__ drift, const HitRec<float>* __restrict__ wire32,
                  const HitRec<double>* __restrict__ wire64, const int32_t* __restrict__ wire_layer,
                  int n_layers, HitRec<float>* __restrict__ out32, HitRec<double>* __restrict__ out64,
-                 int32_t* __restrict__ layer_off, float* __restrict__ ev_maxdrift, int32_t* __restrict__ orig) {
+                 int32_t* __restrict__ layer_off, float* __restrict__ ev_maxdrift, int32_t* __restrict__ orig,
+                 float* __restrict__ out_phi, float* __restrict__ layer_ext) {
   __shared__ int s_layer[RKN_MAX_HITS_PER_EVENT];
+  __shared__ float s_phi[RKN_MAX_HITS_PER_EVENT];
   __shared__ int s_count[RKN_MAX_LAYERS + 1];
+  __shared__ unsigned int s_ext[RKN_MAX_LAYERS];
   __shared__ unsigned int s_max;
   const int e = blockIdx.x, tid = threadIdx.x;
   const int base = ev_off[e], n = ev_off[e + 1] - base;
   for (int l = tid; l <= n_layers; l += blockDim.x) s_count[l] = 0;
+  for (int l = tid; l < n_layers; l += blockDim.x) s_ext[l] = 0u;
   if (tid == 0) s_max = 0u;
   __syncthreads();
   unsigned int mymax = 0u;
   for (int i = tid; i < n; i += blockDim.x) {
-    const int l = wire_layer[wire_id[base + i]];
+    const int w = wire_id[base + i];
+    const int l = wire_layer[w];
     s_layer[i] = l;
     atomicAdd(&s_count[l], 1);
     const unsigned int bits = __float_as_uint(drift[base + i]);
     mymax = bits > mymax ? bits : mymax;
+    const HitRec<float> r = wire32[w];
+    const float phi = atan2f(r.my, r.mx);
+    s_phi[i] = phi;
+    float ext = 0.0f;
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      float d = atan2f(r.my + sgn * r.L * r.uy, r.mx + sgn * r.L * r.ux) - phi;
+      d = d > kPi ? d - 2.0f * kPi : (d < -kPi ? d + 2.0f * kPi : d);
+      ext = fmaxf(ext, fabsf(d));
+    }
+    atomicMax(&s_ext[l], __float_as_uint(ext));
   }
   atomicMax(&s_max, mymax);
   __syncthreads();
@@ -109,13 +132,16 @@ prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__
     }
     s_count[n_layers] = acc;
     for (int l = 0; l <= n_layers; ++l) layer_off[(size_t)e * (n_layers + 1) + l] = s_count[l];
+    for (int l = 0; l < n_layers; ++l) layer_ext[(size_t)e * n_layers + l] = __uint_as_float(s_ext[l]);
     ev_maxdrift[e] = __uint_as_float(s_max);
   }
   __syncthreads();
   for (int i = tid; i < n; i += blockDim.x) {
     const int l = s_layer[i];
+    const float phi = s_phi[i];
     int rank = s_count[l];
-    for (int j = 0; j < i; ++j) rank += (s_layer[j] == l);
+    for (int j = 0; j < n; ++j)
+      rank += (s_layer[j] == l) && (s_phi[j] < phi || (s_phi[j] == phi && j < i));
     const int w = wire_id[base + i];
     HitRec<float> r32 = wire32[w];
     HitRec<double> r64 = wire64[w];
@@ -124,6 +150,7 @@ prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__
     out32[base + rank] = r32;
     out64[base + rank] = r64;
     orig[base + rank] = i;
+    out_phi[base + rank] = phi;
   }
 }
 
@@ -133,7 +160,8 @@ hipError_t launch_prep_hits(rkn_ctx* c, const int32_t* d_wire_id, const float* d
                      c->ev_off.as<int32_t>(), d_wire_id, d_drift, c->wire32.as<HitRec<float>>(),
                      c->wire64.as<HitRec<double>>(), c->wire_layer.as<int32_t>(), c->n_layers,
                      c->hits32.as<HitRec<float>>(), c->hits64.as<HitRec<double>>(),
-                     c->layer_off.as<int32_t>(), c->ev_maxdrift.as<float>(), c->hits_orig.as<int32_t>());
+                     c->layer_off.as<int32_t>(), c->ev_maxdrift.as<float>(), c->hits_orig.as<int32_t>(),
+                     c->hits_phi.as<float>(), c->layer_ext.as<float>());
   return hipGetLastError();
 }
 
@@ -262,9 +290,11 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   float2* s_field = reinterpret_cast<float2*>(smem);
   HitRec<R>* s_hits = reinterpret_cast<HitRec<R>*>(smem + a.field_bytes);
-  uint32_t* s_tab = reinterpret_cast<uint32_t*>(smem + a.field_bytes + a.hits_bytes);
-  R* s_pts = reinterpret_cast<R*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 4);
+  uint16_t* s_ltab = reinterpret_cast<uint16_t*>(smem + a.field_bytes + a.hits_bytes);
+  uint32_t* s_sect = reinterpret_cast<uint32_t*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2);
+  R* s_pts = reinterpret_cast<R*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2 + a.sect_bytes);
   uint32_t* s_items = reinterpret_cast<uint32_t*>(s_pts + WAVES * (B + 1) * 3 * 64);
+  __shared__ int s_loff[RKN_MAX_LAYERS + 1];
   __shared__ int s_tile;
   __shared__ double s_red_e[WAVES];
   __shared__ long long s_red_i[WAVES];
@@ -297,20 +327,62 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
 
     if (ev != cur_event) {
       for (int i = tid; i < nh; i += TILE) s_hits[i] = ghits[i];
-      const float D = a.ev_maxdrift[ev] + (float)sqrt(lam) + kBandMargin;
       const int32_t* loff = a.layer_off + (size_t)ev * (a.n_layers + 1);
+      for (int l = tid; l <= a.n_layers; l += TILE) s_loff[l] = loff[l];
+      // radial bins: the layers whose band, widened by the event's largest drift +
+      // sqrt(lambda) + 1 mm, meets the bin: [l0, l1p) packed as l0 | l1p << 8
+      const float D = a.ev_maxdrift[ev] + (float)sqrt(lam) + kBandMargin;
       for (int b = tid; b < kTabBins; b += TILE) {
         const float lo_r = (float)b, hi_r = b == kTabBins - 1 ? INFINITY : (float)(b + 1);
         int l0 = 0;
         while (l0 < a.n_layers && a.layer_r[l0].y + D < lo_r) ++l0;
         int l1 = a.n_layers - 1;
         while (l1 >= 0 && a.layer_r[l1].x - D > hi_r) --l1;
-        uint32_t lo = 0, hi = 0;
-        if (l0 <= l1) {
-          lo = (uint32_t)loff[l0];
-          hi = (uint32_t)loff[l1 + 1];
+        s_ltab[b] = (uint16_t)(l0 | ((l1 + 1) << 8));
+      }
+      // layer x azimuth sector: the circular run of a layer's hits (sorted by the
+      // azimuth of the wire centre) that a block whose middle point lies in the
+      // sector can reach. A kept pair needs a wire point within
+      // rho = d + sqrt(lambda) + margin + B h / 2 of the middle point; two points at
+      // radii >= r - rho and r that close differ in azimuth by at most
+      // 2 asin(rho / (2 (r - rho))), and the wire's own azimuth spans its centre's
+      // +- the layer's half-extent.
+      const float rho = a.ev_maxdrift[ev] + (float)sqrt(lam) + kCullMargin + 0.5f * (float)(B * a.h);
+      const float* gphi = a.hits_phi + hbase;
+      for (int q = tid; q < a.n_layers * kSectors; q += TILE) {
+        const int l = q / kSectors, k = q - l * kSectors;
+        const int lb = loff[l], nl = loff[l + 1] - lb;
+        uint32_t ent = 0;
+        if (nl > 0) {
+          const float rl = a.layer_r[l].x - rho;
+          const float ratio = rl > 0.0f ? rho / (2.0f * rl) : 2.0f;
+          const float dphi = ratio < 1.0f ? 2.0f * asinf(ratio) : kPi;
+          const float W = a.layer_ext[(size_t)ev * a.n_layers + l] + dphi + 2e-3f;
+          if (W >= kPi) {
+            ent = (uint32_t)nl << 16;
+          } else {
+            const float a0 = -kPi + (2.0f * kPi / kSectors) * k, a1 = a0 + 2.0f * kPi / kSectors;
+            auto inside = [&](int j) {
+              const float ph = gphi[lb + j];
+              if (ph >= a0 && ph <= a1) return true;
+              float d1 = a0 - ph, d2 = ph - a1;
+              d1 -= 2.0f * kPi * floorf(d1 / (2.0f * kPi));
+              d2 -= 2.0f * kPi * floorf(d2 / (2.0f * kPi));
+              return fminf(d1, d2) <= W;
+            };
+            int cnt = 0, start = -1;
+            bool prev = inside(nl - 1);
+            for (int j = 0; j < nl; ++j) {
+              const bool in = inside(j);
+              cnt += in;
+              if (in && !prev && start < 0) start = j;
+              prev = in;
+            }
+            if (cnt == nl) start = 0;
+            ent = cnt > 0 ? ((uint32_t)start | ((uint32_t)cnt << 16)) : 0u;
+          }
         }
-        s_tab[b] = lo | (hi << 16);
+        s_sect[q] = ent;
       }
       cur_event = ev;
     }
@@ -395,27 +467,41 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       // clamp in float first: fminf/fmaxf map NaN to the bound, so the index is in range
       const int b_lo = (int)fminf(fmaxf(rmin, 0.0f), (float)(kTabBins - 1));
       const int b_hi = (int)fminf(fmaxf(rmax, 0.0f), (float)(kTabBins - 1));
-      // each lane walks its own band range; hit records are gathered from LDS
-      const int my_lo = (int)(s_tab[b_lo] & 0xffffu);
-      const int my_n = valid ? max((int)(s_tab[b_hi] >> 16) - my_lo, 0) : 0;
-      const int kmax = wave_max_i32(my_n);
+      // candidates: per layer whose band meets the block's radial range, the run of
+      // hits that can reach the azimuth sector of the block's middle point; each lane
+      // walks its own runs, hit records gathered from LDS
+      const int L0 = s_ltab[b_lo] & 0xff, L1p = s_ltab[b_hi] >> 8;
+      const int n_lay = valid ? max(L1p - L0, 0) : 0;
+      int sect = (int)((atan2f((float)cy, (float)cx) + kPi) * (kSectors / (2.0f * kPi)));
+      sect = sect < 0 ? 0 : (sect > kSectors - 1 ? kSectors - 1 : sect);
+      const int lay_max = wave_max_i32(n_lay);
       int n_items = 0;
-      for (int k = 0; k < kmax; ++k) {
-        const bool act = k < my_n;
-        const int hh = act ? my_lo + k : 0;
-        const HitRec<R> w = s_hits[hh];
-        const R rx = cx - w.mx, ry = cy - w.my, rz = cz - w.mz;
-        const R tt = rx * w.ux + ry * w.uy + rz * w.uz;
-        const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
-        const R thr = Kcull + w.drift;
-        const bool pass = act && (d2 <= thr * thr);
-        const uint64_t m = __ballot(pass);
-        if (m) {
-          if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
-          n_items += (int)__popcll(m);
-          if (n_items > kCap - 64) {
-            flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B, sqrt_lam);
-            n_items = 0;
+      for (int dl = 0; dl < lay_max; ++dl) {
+        const bool has = dl < n_lay;
+        const int l = has ? L0 + dl : 0;
+        const uint32_t ent = has ? s_sect[l * kSectors + sect] : 0u;
+        const int start = (int)(ent & 0xffffu), cnt = (int)(ent >> 16);
+        const int lb = s_loff[l], nl = s_loff[l + 1] - lb;
+        const int kmax = wave_max_i32(cnt);
+        for (int k = 0; k < kmax; ++k) {
+          const bool act = k < cnt;
+          int idx = start + k;
+          idx -= idx >= nl ? nl : 0;
+          const int hh = act ? lb + idx : 0;
+          const HitRec<R> w = s_hits[hh];
+          const R rx = cx - w.mx, ry = cy - w.my, rz = cz - w.mz;
+          const R tt = rx * w.ux + ry * w.uy + rz * w.uz;
+          const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
+          const R thr = Kcull + w.drift;
+          const bool pass = act && (d2 <= thr * thr);
+          const uint64_t m = __ballot(pass);
+          if (m) {
+            if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
+            n_items += (int)__popcll(m);
+            if (n_items > kCap - 64) {
+              flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B, sqrt_lam);
+              n_items = 0;
+            }
           }
         }
       }
@@ -546,12 +632,18 @@ event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restr
   }
 }
 
+// LDS bytes of the layer x sector candidate table (uint32 entries, 256-byte rounded).
+static size_t sect_table_bytes(const rkn_ctx* c) {
+  return ((size_t)std::max(c->n_layers, 1) * kSectors * 4 + 255) & ~(size_t)255;
+}
+
 // LDS bytes of one workgroup of scan_kernel<R, FIELD, B, WAVES>.
 static size_t scan_lds_bytes(const rkn_ctx* c, size_t rsize, int field, int B, int waves) {
   const size_t hits = ((size_t)c->max_hits_event * (rsize == 4 ? sizeof(HitRec<float>) : sizeof(HitRec<double>)) +
                        255) & ~(size_t)255;
   const size_t fld = field == 1 ? (((size_t)c->nr * c->nz * sizeof(float2)) + 255) & ~(size_t)255 : 0;
-  return fld + hits + kTabBins * 4 + (size_t)waves * (B + 1) * 3 * 64 * rsize + (size_t)waves * kCap * 4;
+  return fld + hits + kTabBins * 2 + sect_table_bytes(c) + (size_t)waves * (B + 1) * 3 * 64 * rsize +
+         (size_t)waves * kCap * 4;
 }
 
 // Steps per block; 0 picks the default: 6 for the FP32 field-map path (12-wave
@@ -605,6 +697,7 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   const int field_bytes = FIELD == 1 ? ((c->nr * c->nz * (int)sizeof(float2)) + 255) & ~255 : 0;
   a.hits_bytes = hits_bytes;
   a.field_bytes = field_bytes;
+  a.sect_bytes = (int)sect_table_bytes(c);
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
   auto kern = scan_kernel<R, FIELD, B, WAVES, MODE>;
@@ -680,6 +773,8 @@ hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_til
   a.layer_off = c->layer_off.as<int32_t>();
   a.layer_r = c->layer_r.as<float2>();
   a.ev_maxdrift = c->ev_maxdrift.as<float>();
+  a.hits_phi = c->hits_phi.as<float>();
+  a.layer_ext = c->layer_ext.as<float>();
   a.n_layers = c->n_layers;
   a.tiles = d_tiles;
   a.n_tiles = n_tiles;
@@ -718,6 +813,8 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   a.layer_off = c->layer_off.as<int32_t>();
   a.layer_r = c->layer_r.as<float2>();
   a.ev_maxdrift = c->ev_maxdrift.as<float>();
+  a.hits_phi = c->hits_phi.as<float>();
+  a.layer_ext = c->layer_ext.as<float>();
   a.n_layers = c->n_layers;
   a.tiles = d_tiles;
   a.windows = d_windows;
