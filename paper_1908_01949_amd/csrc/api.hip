@@ -285,7 +285,7 @@ rkn_status rkn_upload_hits(rkn_ctx* c, int32_t n_events, const int32_t* ev_off, 
   if (e == hipSuccess) e = c->hits_orig.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(H, 1));
   if (e == hipSuccess) e = c->hits_phi.ensure(sizeof(float) * (size_t)std::max<int64_t>(H, 1));
   if (e == hipSuccess)
-    e = c->layer_ext.ensure(sizeof(float) * (size_t)std::max(n_events, 1) * (size_t)std::max(c->n_layers, 1));
+    e = c->layer_ext.ensure(sizeof(float2) * (size_t)std::max(n_events, 1) * (size_t)std::max(c->n_layers, 1));
   if (e == hipSuccess) {
     c->n_events = n_events;
     e = rkn::launch_prep_hits(c, d_wid.as<int32_t>(), d_drift.as<float>());

@@ -133,8 +133,8 @@ struct rkn_ctx {
   rkn::DevBuf ev_off, hits32, hits64, layer_off, ev_maxdrift;
   rkn::DevBuf hits_wire;             // int32 wire id per hit, upload order
   rkn::DevBuf hits_orig;             // int32 original index within its event, per layer-ordered hit
-  rkn::DevBuf hits_phi;              // float azimuth of the wire centre, per layer-ordered hit
-  rkn::DevBuf layer_ext;             // float [n_events][n_layers] largest wire azimuth half-extent
+  rkn::DevBuf hits_phi;              // float twisted azimuth psi of the wire centre, per layer-ordered hit
+  rkn::DevBuf layer_ext;             // float2 [n_events][n_layers] (dphi/dz of the layer's wires, psi deviation)
   rkn::DevBuf hough_acc, hough_max, hough_cand_n, hough_cand, hough_slots, hough_nsel;
 
   // per-call work buffers

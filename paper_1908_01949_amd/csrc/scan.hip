@@ -33,7 +33,7 @@ constexpr int kCap = 192;          // work-list entries per wave
 constexpr int kTabBins = 1024;     // 1 mm radial bins, the last one open-ended
 constexpr float kBandMargin = 1.0f;   // radial band table
 constexpr float kCullMargin = 0.05f;  // sphere test: covers FP32 rounding of the test (~1e-2 mm)
-constexpr int kSectors = 32;          // azimuthal sectors of the candidate table
+constexpr int kSectors = 64;          // twisted-azimuth sectors of the candidate table
 constexpr float kPi = 3.14159265358979f;
 
 struct ScanArgs {
@@ -44,8 +44,8 @@ struct ScanArgs {
   const int32_t* layer_off;   // [n_events][n_layers+1]
   const float2* layer_r;      // (rmin, rmax) per layer
   const float* ev_maxdrift;
-  const float* hits_phi;      // azimuth of each layer-ordered hit's wire centre
-  const float* layer_ext;     // [n_events][n_layers] largest azimuth half-extent of a wire
+  const float* hits_phi;      // twisted azimuth psi of each layer-ordered hit's wire centre
+  const float2* layer_twist;  // [n_events][n_layers] (dphi/dz of the layer's wires, psi deviation)
   int n_layers;
   int sect_bytes;             // LDS bytes reserved for the layer x sector table
   int hits_bytes;             // LDS bytes reserved for hit records
@@ -80,48 +80,75 @@ struct ScanArgs {
 
 // ---------------------------------------------------------------------------------
 // Upload-time preparation: per event, order the hits by layer and, within a layer,
-// by the azimuth of the wire centre (ties by upload order); build the FP32/FP64 hit
-// records, the per-layer offsets, the event's largest drift, each hit's azimuth and
-// per layer the largest azimuth half-extent of a wire over |t| <= L (a stereo wire
-// turns in azimuth along z; the extremes are at its ends).
+// by the twisted azimuth psi = phi(m) - s_l m_z of the wire centre m (ties by upload
+// order), where s_l = dphi/dz of the layer's stereo wires (taken from the layer's
+// first hit). Along a wire, phi - s_l z stays within dev_l of psi; the kernel uses
+// (s_l, dev_l) per layer to turn a block's middle point into a psi window. Also
+// builds the FP32/FP64 hit records, the per-layer offsets and the event's largest
+// drift.
+__device__ __forceinline__ float wrap_pi(float d) {
+  return d >= kPi ? d - 2.0f * kPi : (d < -kPi ? d + 2.0f * kPi : d);
+}
+
 __global__ void __launch_bounds__(256)
 prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__ wire_id,
                  const float* __restrict__ drift, const HitRec<float>* __restrict__ wire32,
                  const HitRec<double>* __restrict__ wire64, const int32_t* __restrict__ wire_layer,
                  int n_layers, HitRec<float>* __restrict__ out32, HitRec<double>* __restrict__ out64,
                  int32_t* __restrict__ layer_off, float* __restrict__ ev_maxdrift, int32_t* __restrict__ orig,
-                 float* __restrict__ out_phi, float* __restrict__ layer_ext) {
+                 float* __restrict__ out_psi, float2* __restrict__ layer_twist) {
   __shared__ int s_layer[RKN_MAX_HITS_PER_EVENT];
-  __shared__ float s_phi[RKN_MAX_HITS_PER_EVENT];
+  __shared__ float s_psi[RKN_MAX_HITS_PER_EVENT];
   __shared__ int s_count[RKN_MAX_LAYERS + 1];
-  __shared__ unsigned int s_ext[RKN_MAX_LAYERS];
+  __shared__ int s_first[RKN_MAX_LAYERS];
+  __shared__ unsigned int s_dev[RKN_MAX_LAYERS];
+  __shared__ float s_slope[RKN_MAX_LAYERS];
   __shared__ unsigned int s_max;
   const int e = blockIdx.x, tid = threadIdx.x;
   const int base = ev_off[e], n = ev_off[e + 1] - base;
   for (int l = tid; l <= n_layers; l += blockDim.x) s_count[l] = 0;
-  for (int l = tid; l < n_layers; l += blockDim.x) s_ext[l] = 0u;
+  for (int l = tid; l < n_layers; l += blockDim.x) {
+    s_dev[l] = 0u;
+    s_first[l] = 0x7fffffff;
+  }
   if (tid == 0) s_max = 0u;
   __syncthreads();
   unsigned int mymax = 0u;
   for (int i = tid; i < n; i += blockDim.x) {
-    const int w = wire_id[base + i];
-    const int l = wire_layer[w];
+    const int l = wire_layer[wire_id[base + i]];
     s_layer[i] = l;
     atomicAdd(&s_count[l], 1);
+    atomicMin(&s_first[l], i);
     const unsigned int bits = __float_as_uint(drift[base + i]);
     mymax = bits > mymax ? bits : mymax;
-    const HitRec<float> r = wire32[w];
-    const float phi = atan2f(r.my, r.mx);
-    s_phi[i] = phi;
-    float ext = 0.0f;
-    for (int sgn = -1; sgn <= 1; sgn += 2) {
-      float d = atan2f(r.my + sgn * r.L * r.uy, r.mx + sgn * r.L * r.ux) - phi;
-      d = d > kPi ? d - 2.0f * kPi : (d < -kPi ? d + 2.0f * kPi : d);
-      ext = fmaxf(ext, fabsf(d));
-    }
-    atomicMax(&s_ext[l], __float_as_uint(ext));
   }
   atomicMax(&s_max, mymax);
+  __syncthreads();
+  for (int l = tid; l < n_layers; l += blockDim.x) {
+    float sl = 0.0f;
+    if (s_first[l] < n) {
+      const HitRec<float> r = wire32[wire_id[base + s_first[l]]];
+      const float r2 = r.mx * r.mx + r.my * r.my;
+      sl = (fabsf(r.uz) > 1e-6f && r2 > 0.0f) ? (r.mx * r.uy - r.my * r.ux) / (r2 * r.uz) : 0.0f;
+    }
+    s_slope[l] = sl;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int l = s_layer[i];
+    const float sl = s_slope[l];
+    const HitRec<float> r = wire32[wire_id[base + i]];
+    const float phi = atan2f(r.my, r.mx);
+    s_psi[i] = wrap_pi(phi - sl * r.mz);
+    float dev = 0.0f;
+    for (int q = -2; q <= 2; ++q) {
+      if (q == 0) continue;
+      const float t = 0.5f * (float)q * r.L;
+      const float d = wrap_pi(atan2f(r.my + t * r.uy, r.mx + t * r.ux) - phi) - sl * r.uz * t;
+      dev = fmaxf(dev, fabsf(d));
+    }
+    atomicMax(&s_dev[l], __float_as_uint(dev));
+  }
   __syncthreads();
   if (tid == 0) {
     int acc = 0;
@@ -132,16 +159,19 @@ prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__
     }
     s_count[n_layers] = acc;
     for (int l = 0; l <= n_layers; ++l) layer_off[(size_t)e * (n_layers + 1) + l] = s_count[l];
-    for (int l = 0; l < n_layers; ++l) layer_ext[(size_t)e * n_layers + l] = __uint_as_float(s_ext[l]);
+    // the deviation is sampled at t = +-L/2, +-L; its curvature term is bounded by
+    // doubling the sampled maximum
+    for (int l = 0; l < n_layers; ++l)
+      layer_twist[(size_t)e * n_layers + l] = make_float2(s_slope[l], 2.0f * __uint_as_float(s_dev[l]));
     ev_maxdrift[e] = __uint_as_float(s_max);
   }
   __syncthreads();
   for (int i = tid; i < n; i += blockDim.x) {
     const int l = s_layer[i];
-    const float phi = s_phi[i];
+    const float psi = s_psi[i];
     int rank = s_count[l];
     for (int j = 0; j < n; ++j)
-      rank += (s_layer[j] == l) && (s_phi[j] < phi || (s_phi[j] == phi && j < i));
+      rank += (s_layer[j] == l) && (s_psi[j] < psi || (s_psi[j] == psi && j < i));
     const int w = wire_id[base + i];
     HitRec<float> r32 = wire32[w];
     HitRec<double> r64 = wire64[w];
@@ -150,7 +180,7 @@ prep_hits_kernel(const int32_t* __restrict__ ev_off, const int32_t* __restrict__
     out32[base + rank] = r32;
     out64[base + rank] = r64;
     orig[base + rank] = i;
-    out_phi[base + rank] = phi;
+    out_psi[base + rank] = psi;
   }
 }
 
@@ -161,7 +191,7 @@ hipError_t launch_prep_hits(rkn_ctx* c, const int32_t* d_wire_id, const float* d
                      c->wire64.as<HitRec<double>>(), c->wire_layer.as<int32_t>(), c->n_layers,
                      c->hits32.as<HitRec<float>>(), c->hits64.as<HitRec<double>>(),
                      c->layer_off.as<int32_t>(), c->ev_maxdrift.as<float>(), c->hits_orig.as<int32_t>(),
-                     c->hits_phi.as<float>(), c->layer_ext.as<float>());
+                     c->hits_phi.as<float>(), c->layer_ext.as<float2>());
   return hipGetLastError();
 }
 
@@ -295,6 +325,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   R* s_pts = reinterpret_cast<R*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2 + a.sect_bytes);
   uint32_t* s_items = reinterpret_cast<uint32_t*>(s_pts + WAVES * (B + 1) * 3 * 64);
   __shared__ int s_loff[RKN_MAX_LAYERS + 1];
+  __shared__ float s_slope[RKN_MAX_LAYERS];
   __shared__ int s_tile;
   __shared__ double s_red_e[WAVES];
   __shared__ long long s_red_i[WAVES];
@@ -340,32 +371,33 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         while (l1 >= 0 && a.layer_r[l1].x - D > hi_r) --l1;
         s_ltab[b] = (uint16_t)(l0 | ((l1 + 1) << 8));
       }
-      // layer x azimuth sector: the circular run of a layer's hits (sorted by the
-      // azimuth of the wire centre) that a block whose middle point lies in the
-      // sector can reach. A kept pair needs a wire point within
-      // rho = d + sqrt(lambda) + margin + B h / 2 of the middle point; two points at
-      // radii >= r - rho and r that close differ in azimuth by at most
-      // 2 asin(rho / (2 (r - rho))), and the wire's own azimuth spans its centre's
-      // +- the layer's half-extent.
+      // layer x twisted-azimuth sector: the circular run of a layer's hits (sorted by
+      // psi) that a block whose middle point c has psi_c = phi_c - s_l z_c in the
+      // sector can reach. A kept pair needs a wire point w within
+      // rho = d + sqrt(lambda) + margin + B h / 2 of c; then |phi_w - phi_c| <=
+      // 2 asin(rho / (2 (r_l - rho))) (radii >= r_l - rho and r_l),
+      // |z_w - z_c| <= rho, and phi_w - s_l z_w is within dev_l of the hit's psi.
       const float rho = a.ev_maxdrift[ev] + (float)sqrt(lam) + kCullMargin + 0.5f * (float)(B * a.h);
-      const float* gphi = a.hits_phi + hbase;
+      const float* gpsi = a.hits_phi + hbase;
+      for (int l = tid; l < a.n_layers; l += TILE) s_slope[l] = a.layer_twist[(size_t)ev * a.n_layers + l].x;
       for (int q = tid; q < a.n_layers * kSectors; q += TILE) {
         const int l = q / kSectors, k = q - l * kSectors;
         const int lb = loff[l], nl = loff[l + 1] - lb;
         uint32_t ent = 0;
         if (nl > 0) {
+          const float2 tw = a.layer_twist[(size_t)ev * a.n_layers + l];
           const float rl = a.layer_r[l].x - rho;
           const float ratio = rl > 0.0f ? rho / (2.0f * rl) : 2.0f;
           const float dphi = ratio < 1.0f ? 2.0f * asinf(ratio) : kPi;
-          const float W = a.layer_ext[(size_t)ev * a.n_layers + l] + dphi + 2e-3f;
+          const float W = dphi + fabsf(tw.x) * rho + tw.y + 2e-3f;
           if (W >= kPi) {
             ent = (uint32_t)nl << 16;
           } else {
             const float a0 = -kPi + (2.0f * kPi / kSectors) * k, a1 = a0 + 2.0f * kPi / kSectors;
             auto inside = [&](int j) {
-              const float ph = gphi[lb + j];
-              if (ph >= a0 && ph <= a1) return true;
-              float d1 = a0 - ph, d2 = ph - a1;
+              const float ps = gpsi[lb + j];
+              if (ps >= a0 && ps <= a1) return true;
+              float d1 = a0 - ps, d2 = ps - a1;
               d1 -= 2.0f * kPi * floorf(d1 / (2.0f * kPi));
               d2 -= 2.0f * kPi * floorf(d2 / (2.0f * kPi));
               return fminf(d1, d2) <= W;
@@ -472,13 +504,15 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       // walks its own runs, hit records gathered from LDS
       const int L0 = s_ltab[b_lo] & 0xff, L1p = s_ltab[b_hi] >> 8;
       const int n_lay = valid ? max(L1p - L0, 0) : 0;
-      int sect = (int)((atan2f((float)cy, (float)cx) + kPi) * (kSectors / (2.0f * kPi)));
-      sect = sect < 0 ? 0 : (sect > kSectors - 1 ? kSectors - 1 : sect);
+      const float phic = atan2f((float)cy, (float)cx);
       const int lay_max = wave_max_i32(n_lay);
       int n_items = 0;
       for (int dl = 0; dl < lay_max; ++dl) {
         const bool has = dl < n_lay;
         const int l = has ? L0 + dl : 0;
+        const float psic = wrap_pi(phic - s_slope[l] * (float)cz);
+        int sect = (int)((psic + kPi) * (kSectors / (2.0f * kPi)));
+        sect = sect < 0 ? 0 : (sect > kSectors - 1 ? kSectors - 1 : sect);
         const uint32_t ent = has ? s_sect[l * kSectors + sect] : 0u;
         const int start = (int)(ent & 0xffffu), cnt = (int)(ent >> 16);
         const int lb = s_loff[l], nl = s_loff[l + 1] - lb;
@@ -774,7 +808,7 @@ hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_til
   a.layer_r = c->layer_r.as<float2>();
   a.ev_maxdrift = c->ev_maxdrift.as<float>();
   a.hits_phi = c->hits_phi.as<float>();
-  a.layer_ext = c->layer_ext.as<float>();
+  a.layer_twist = c->layer_ext.as<float2>();
   a.n_layers = c->n_layers;
   a.tiles = d_tiles;
   a.n_tiles = n_tiles;
@@ -814,7 +848,7 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   a.layer_r = c->layer_r.as<float2>();
   a.ev_maxdrift = c->ev_maxdrift.as<float>();
   a.hits_phi = c->hits_phi.as<float>();
-  a.layer_ext = c->layer_ext.as<float>();
+  a.layer_twist = c->layer_ext.as<float2>();
   a.n_layers = c->n_layers;
   a.tiles = d_tiles;
   a.windows = d_windows;
