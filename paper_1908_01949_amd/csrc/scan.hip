@@ -86,6 +86,20 @@ struct ScanArgs {
 // (s_l, dev_l) per layer to turn a block's middle point into a psi window. Also
 // builds the FP32/FP64 hit records, the per-layer offsets and the event's largest
 // drift.
+// Azimuth for the sector lookup: octant reduction and an odd degree-7 polynomial
+// for atan on [0, 1] (our least-squares fit; |error| < 1e-4 rad, far inside the
+// table's 2e-3 rad margin).
+__device__ __forceinline__ float sector_atan2(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float hi = fmaxf(ax, ay), lo = fminf(ax, ay);
+  const float t = hi > 0.0f ? lo * __builtin_amdgcn_rcpf(hi) : 0.0f;
+  const float u = t * t;
+  float r = t * fmaf(fmaf(fmaf(-0.03898633f, u, 0.14626420f), u, -0.32117486f), u, 0.99921381f);
+  r = ay > ax ? 0.5f * kPi - r : r;
+  r = x < 0.0f ? kPi - r : r;
+  return y < 0.0f ? -r : r;
+}
+
 __device__ __forceinline__ float wrap_pi(float d) {
   return d >= kPi ? d - 2.0f * kPi : (d < -kPi ? d + 2.0f * kPi : d);
 }
@@ -504,10 +518,9 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       // walks its own runs, hit records gathered from LDS
       const int L0 = s_ltab[b_lo] & 0xff, L1p = s_ltab[b_hi] >> 8;
       const int n_lay = valid ? max(L1p - L0, 0) : 0;
-      const float phic = atan2f((float)cy, (float)cx);
-      const int lay_max = wave_max_i32(n_lay);
+      const float phic = sector_atan2((float)cy, (float)cx);
       int n_items = 0;
-      for (int dl = 0; dl < lay_max; ++dl) {
+      for (int dl = 0; __ballot(dl < n_lay) != 0; ++dl) {
         const bool has = dl < n_lay;
         const int l = has ? L0 + dl : 0;
         const float psic = wrap_pi(phic - s_slope[l] * (float)cz);
@@ -516,8 +529,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         const uint32_t ent = has ? s_sect[l * kSectors + sect] : 0u;
         const int start = (int)(ent & 0xffffu), cnt = (int)(ent >> 16);
         const int lb = s_loff[l], nl = s_loff[l + 1] - lb;
-        const int kmax = wave_max_i32(cnt);
-        for (int k = 0; k < kmax; ++k) {
+        for (int k = 0; __ballot(k < cnt) != 0; ++k) {
           const bool act = k < cnt;
           int idx = start + k;
           idx -= idx >= nl ? nl : 0;
