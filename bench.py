@@ -82,6 +82,23 @@ def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_ste
         dict(cull_per_step=cull / ss, pairs_per_step=pairs / ss, sample_max_rel_score_err=rel)
 
 
+def measured_traffic():
+    """HBM bytes per scan launch from the committed counter record (FETCH_SIZE and
+    WRITE_SIZE runs scaled by a plain copy's counts), or None when the kernel sources
+    differ from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "scan_kernel_512ev_solenoid_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for fn in ("scan.hip", "device_math.hpp", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1908_01949_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return int(rec["traffic_bytes"]) if rec.get("kernel_source_sha256") == h.hexdigest() else None
+
+
 def _sync_time(fn):
     import torch
     torch.cuda.synchronize()
@@ -290,10 +307,10 @@ def main():
     roof = None
     bwaves = tile // 64
     if work is not None:
-        f_alg = flops.per_seed_step("rz", work["cull_per_step"], work["pairs_per_step"])
+        f_alg = flops.per_seed_step("rz", work["pairs_per_step"])
         achieved = f_alg * seed_steps / (np.mean(ms_s) * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=round(achieved, 3), peak=flops.PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / flops.PEAK_FP32_TFLOPS, 4), traffic=None,
+                    frac=round(achieved / flops.PEAK_FP32_TFLOPS, 4), traffic=measured_traffic(),
                     flops_per_seed_step=round(f_alg, 2),
                     kernel=f"scan_kernel<float, rz field, {bsteps}-step blocks, {bwaves} waves>")
     out = {
