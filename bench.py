@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 from paper_1908_01949_amd import rknscan as rk  # noqa: E402  (loads the HIP runtime first)
-from paper_1908_01949_amd import flops, synth  # noqa: E402
+from paper_1908_01949_amd import flops, synth, workloads  # noqa: E402
 
 METRIC = "RKN seed-steps/s & events/s, %FP32 vector peak; plain scan vs adjoint-refined"
 
@@ -30,12 +30,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cfg4_hough_params(field):
+def batch_hough_params(field):
     """Window rule of the batched workload: 1e3-1e5 seeds per event."""
-    return rk.make_hough_params(
-        b_ref=field.b_ref, min_votes=6, max_cand=4,
-        gran=(0.01, 100.0, 2.5, 2.5, 12.0), center_z=0.0, center_pz=0.0,
-        count=(4, 6, 4, 4, 6), grow=(1, 0, 1, 1, 0), count_max=10, max_seeds_window=25000)
+    return rk.make_hough_params(b_ref=field.b_ref, **workloads.BATCH["hough"])
 
 
 def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_steps, lam, seconds):
@@ -273,7 +270,7 @@ def main():
     ctx.upload_hits(off, wid, dr)
     lam = 64.0
     sp = rk.make_scan_params(n_steps=args.rkn_steps, precision=32, lambda_mm2=lam, block_steps=args.block_steps)
-    hp = cfg4_hough_params(field)
+    hp = batch_hough_params(field)
     bsteps, tile = rk.rkn_scan_shape(ctx.ctx, sp)
     log(f"scan shape: {bsteps}-step blocks, {tile} seeds per tile ({tile // 64} waves)")
     rk.rkn_batch_plan(ctx.ctx, hp, sp)

@@ -1,0 +1,178 @@
+"""GPU parity at the full sizes of the measured workloads, in the launch configuration
+the benchmark times: per-seed scores on sampled seeds that the oracle computes one by
+one, the best seed per event against the sample (no sampled seed may beat it beyond
+the near-tie rule) and the oracle's score of the GPU's pick, windows exactly against
+the oracle's Hough stage, and the Gauss-Newton refinement of the batch's best seeds."""
+import numpy as np
+import pytest
+
+from paper_1908_01949_amd import synth, workloads
+from tests import parity_util as pu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rk():
+    from paper_1908_01949_amd import rknscan
+    rknscan.load_library()
+    return rknscan
+
+
+def _window_index_to_seeds(orc, windows, idx):
+    sizes = np.array([int(np.prod(w["count"].astype(np.int64))) for w in windows])
+    base = np.concatenate([[0], np.cumsum(sizes)])
+    kw = np.searchsorted(base, idx, side="right") - 1
+    seeds = np.array([orc.window_seed(windows[k], int(g - base[k])) for k, g in zip(kw, idx)])
+    return windows["event"][kw].astype(np.int32), seeds
+
+
+def _check_sample(orc, prm, off, wid, dr, windows, score, rng, n_sample):
+    total = score.size
+    g = np.sort(rng.choice(total, size=min(n_sample, total), replace=False))
+    se, seeds = _window_index_to_seeds(orc, windows, g)
+    osc, onin, _, _ = orc.scan_seeds(prm, off, wid, dr, se, seeds, mode=1)
+    rel = pu.check_scores(score[g], osc)
+    return g, se, osc, rel
+
+
+def _check_best_against_sample(orc, prm, off, wid, dr, windows, bi, bs, se, osc, events):
+    """The GPU's pick: its oracle score matches, and no sampled seed of the event is
+    lower beyond the near-tie rule."""
+    picks = np.array([bi[e] for e in events])
+    pe, pseeds = _window_index_to_seeds(orc, windows, picks)
+    psc, _, _, _ = orc.scan_seeds(prm, off, wid, dr, pe, pseeds, mode=1)
+    pu.check_scores(np.array([bs[e] for e in events]), psc)
+    for e, s in zip(events, psc):
+        sample = osc[se == e]
+        if sample.size:
+            assert s <= sample.min() * (1 + pu.NEAR_TIE) + 1e-9, (e, s, sample.min())
+
+
+def test_multi_turn_16_5_full(rk, geo, ufield, orc_u):
+    """2-3 pass event with 30 % noise, 16^5 = 1 048 576 seeds, 6000 FP32 steps."""
+    wl = workloads.MULTI_TURN
+    ev = synth.event_multi_turn(geo, ufield, 0)
+    off, wid, dr = synth.pack_events([ev])
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(ufield); c.upload_hits(off, wid, dr)
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], wl["half_width"], [wl["count"]] * 5)])
+    p = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    n = wl["count"] ** 5
+    score = np.zeros(n); nin = np.zeros(n, np.int32); bi = np.zeros(1, np.int64); bs = np.zeros(1)
+    rk.rkn_scan_windows(c.ctx, p, w, score, nin, bi, bs)
+    assert bi[0] == int(np.argmin(score)) and bs[0] == score.min()
+    prm = orc_u.params(n_steps=wl["n_steps"])
+    g, se, osc, rel = _check_sample(orc_u, prm, off, wid, dr, w, score, np.random.default_rng(5), 384)
+    print(f"16^5: max rel score error on {g.size} sampled seeds {rel:.2e}", flush=True)
+    _check_best_against_sample(orc_u, prm, off, wid, dr, w, bi, bs, se, osc, [0])
+    c.close()
+
+
+def test_hough_event_12_5_full(rk, geo, sfield, orc_s):
+    """150-hit event (20 % noise) in the solenoid map: Hough windows of 12^5 seeds."""
+    wl = workloads.HOUGH_EVENT
+    ev = synth.event_fixed_total(geo, sfield, 0, n_total=150, noise_frac=0.2)
+    off, wid, dr = synth.pack_events([ev])
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    kw = dict(b_ref=sfield.b_ref, **wl["hough"])
+    w = rk.rkn_hough_seed_windows(c.ctx, rk.make_hough_params(**kw))
+    ow = orc_s.hough_seed_windows(orc_s.hough_params(**kw), off, wid)
+    assert len(w) >= 1 and np.array_equal(ow["count"], w["count"])
+    np.testing.assert_allclose(ow["center"], w["center"], rtol=0, atol=1e-11)
+    assert np.all(np.prod(w["count"].astype(np.int64), axis=1) == 12 ** 5)
+    p = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    n = int(np.prod(w["count"].astype(np.int64), axis=1).sum())
+    score = np.zeros(n); bi = np.zeros(1, np.int64); bs = np.zeros(1)
+    rk.rkn_scan_windows(c.ctx, p, w, score, None, bi, bs)
+    prm = orc_s.params(n_steps=wl["n_steps"])
+    g, se, osc, rel = _check_sample(orc_s, prm, off, wid, dr, w, score, np.random.default_rng(6), 384)
+    print(f"Hough 12^5 x {len(w)}: max rel score error on {g.size} sampled seeds {rel:.2e}", flush=True)
+    _check_best_against_sample(orc_s, prm, off, wid, dr, w, bi, bs, se, osc, [0])
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def batch(rk, geo, sfield):
+    wl = workloads.BATCH
+    evs = synth.events_batch(geo, sfield, wl["n_events"], seed=0, n_steps=wl["n_steps"])
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    hp = rk.make_hough_params(b_ref=sfield.b_ref, **wl["hough"])
+    sp = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    rk.rkn_batch_plan(c.ctx, hp, sp)
+    ne = len(evs)
+    bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+    rk.rkn_batch_launch(c.ctx, bi, bs)
+    w, score, nin, ev_seed = rk.rkn_batch_results(c.ctx, ne)
+    yield dict(c=c, evs=evs, off=off, wid=wid, dr=dr, windows=w, score=score, ev_seed=ev_seed, bi=bi, bs=bs)
+    c.close()
+
+
+def test_batch_512_full(rk, batch, orc_s, sfield):
+    """512 events, 1e3-1e5 seeds each, one persistent launch replayed from HIP graphs."""
+    wl = workloads.BATCH
+    b = batch
+    ns = b["score"].size
+    print(f"batch: {len(b['windows'])} windows, {ns} seeds", flush=True)
+    # windows of sampled events equal the oracle's Hough stage
+    rng = np.random.default_rng(7)
+    sample_events = np.sort(rng.choice(len(b["evs"]), size=16, replace=False))
+    ohp = orc_s.hough_params(b_ref=sfield.b_ref, **wl["hough"])
+    for e in sample_events:
+        lo, hi = b["off"][e], b["off"][e + 1]
+        ow = orc_s.hough_seed_windows(ohp, np.array([0, hi - lo], np.int32), b["wid"][lo:hi])
+        gw = b["windows"][b["windows"]["event"] == e]
+        assert np.array_equal(ow["count"], gw["count"]), e
+        np.testing.assert_allclose(ow["center"], gw["center"], rtol=0, atol=1e-11)
+    prm = orc_s.params(n_steps=wl["n_steps"])
+    g, se, osc, rel = _check_sample(orc_s, prm, b["off"], b["wid"], b["dr"], b["windows"], b["score"], rng, 384)
+    print(f"batch: max rel score error on {g.size} sampled seeds {rel:.2e}", flush=True)
+    # per-event picks: the launch's argmin equals the scores' argmin; sampled events vs oracle
+    for e in range(len(b["evs"])):
+        lo, hi = b["ev_seed"][e], b["ev_seed"][e + 1]
+        if hi > lo:
+            assert b["bi"][e] == lo + int(np.argmin(b["score"][lo:hi]))
+    _check_best_against_sample(orc_s, prm, b["off"], b["wid"], b["dr"], b["windows"], b["bi"], b["bs"], se, osc,
+                               [int(e) for e in sample_events if b["ev_seed"][e + 1] > b["ev_seed"][e]])
+
+
+def test_refine_top8_of_batch_full(rk, batch, orc_s):
+    """The 8 best seeds per event of the batch (about 4096), 10 Gauss-Newton iterations;
+    sampled seeds against the oracle's own Gauss-Newton from the same start."""
+    wl = workloads.REFINE
+    b = batch
+    c = b["c"]
+    ne = len(b["evs"])
+    idx, sc, s5 = rk.rkn_batch_topk(c.ctx, wl["k"], n_events=ne)
+    ok = idx >= 0
+    ev = np.repeat(np.arange(ne, dtype=np.int32), wl["k"]).reshape(ne, wl["k"])[ok]
+    seeds = s5[ok]
+    p = rk.make_scan_params(n_steps=workloads.BATCH["n_steps"], precision=32)
+    rk.rkn_refine_setup(c.ctx, p, ev, seeds, wl["ckpt_every"])
+    n = ev.size
+    out = np.zeros((n, 5)); phi = np.zeros((n, wl["iters"] + 1))
+    rk.rkn_gn_refine(c.ctx, wl["iters"], np.array(wl["scale"]), out, phi)
+    assert np.all(np.diff(phi, axis=1) <= 0)
+    print(f"refine: {n} seeds, mean Phi {phi[:, 0].mean():.3g} -> {phi[:, -1].mean():.3g}", flush=True)
+    prm = orc_s.params(n_steps=workloads.BATCH["n_steps"])
+    rng = np.random.default_rng(8)
+    worse = []
+    for q in rng.choice(n, size=12, replace=False):
+        e = ev[q]
+        lo, hi = b["off"][e], b["off"][e + 1]
+        so, mo, phio = orc_s.gn_refine(prm, seeds[q], b["wid"][lo:hi], b["dr"][lo:hi], scale=wl["scale"],
+                                       iters=wl["iters"])
+        assert phi[q, 0] == pytest.approx(phio[0], rel=1e-3, abs=1e-3)
+        okj, r, _ = orc_s.residual_jacobian(prm, out[q], b["wid"][lo:hi], b["dr"][lo:hi], mo)
+        assert okj
+        phi_at_gpu = float((r[mo.astype(bool)] ** 2).sum())
+        if phi_at_gpu > phio[-1] * (1 + 1e-3) + 1e-3:
+            worse.append((int(q), phi_at_gpu, float(phio[-1])))
+    # from coarse-grid starts far from the minimum, a step-length choice taken at a
+    # near-tie in FP32 vs FP64 can send the two iterations to different basins; allow
+    # that for at most 2 of the 12 sampled seeds and print them
+    print(f"refine: sampled seeds where the oracle's minimum is lower: {worse}", flush=True)
+    assert len(worse) <= 2, worse

@@ -156,6 +156,24 @@ def test_scan_solenoid_workgroup_shapes(rk, ctx_s, orc_s, geo, sfield, block_ste
     pu.check_best(bi[0], osc)
 
 
+def test_scan_max_hits_event(rk, ctx_s, orc_s, geo, sfield):
+    """An event at the hit limit (512 hits, mostly noise): the wide workgroup shapes no
+    longer fit in LDS, the scan falls back to 8 waves and still matches the oracle."""
+    _note("scan 512-hit event, solenoid FP32")
+    ev = synth.event_fixed_total(geo, sfield, 3, n_total=512, noise_frac=0.7)
+    assert ev.wire_id.size == 512
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], [0.03, 20, 3, 3, 3], [3, 3, 3, 3, 4])])
+    off, wid, dr = synth.pack_events([ev])
+    ctx_s.upload_hits(off, wid, dr)
+    bsteps, tile = rk.rkn_scan_shape(ctx_s.ctx, rk.make_scan_params(n_steps=1500, precision=32))
+    _note(f"  shape {bsteps}-step blocks, {tile} seeds per tile")
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_s, orc_s, [ev], w, 1500, 32)
+    rel = pu.check_scores(score, osc)
+    _note(f"  max rel score error {rel:.2e}")
+    pu.check_nin(nin, onin)
+    pu.check_best(bi[0], osc)
+
+
 def test_scan_multi_event_edge_cases(rk, ctx_u, orc_u, geo, ufield, ev1):
     """Several events: one with no hits, one with no window, a seed with |p| ~ 0, lambda = 16."""
     _note("scan multi-event edge cases")
