@@ -127,9 +127,13 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
     # (a) Gauss-Newton
     p = rk.make_scan_params(n_steps=sp.n_steps, precision=32, lambda_mm2=sp.lambda_mm2)
     nsd = seed_event.size
+    # the checkpoint interval is tuned once (untimed), then used by the timed leg
+    rk.rkn_refine_setup(ctx.ctx, p, seed_event, seeds, 0)
+    _, ckpt, tune_ms = rk.rkn_refine_info(ctx.ctx)
+    log(f"checkpoint tuner: {ckpt} steps (adjoint sweeps for 32/64/128/256: {tune_ms})")
 
     def gn():
-        rk.rkn_refine_setup(ctx.ctx, p, seed_event, seeds, 64)
+        rk.rkn_refine_setup(ctx.ctx, p, seed_event, seeds, ckpt)
         out = np.zeros((nsd, 5)); phi = np.zeros((nsd, gn_iters + 1))
         rk.rkn_gn_refine(ctx.ctx, gn_iters, np.asarray(scale), out, phi)
         return out, phi
@@ -216,7 +220,7 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
     t_a = t_coarse + t_topk + t_gn
     t_b = t_coarse + t_topk + t_rounds
     return dict(
-        seeds=int(nsd), k=k, gn_iters=gn_iters, ckpt_every=64,
+        seeds=int(nsd), k=k, gn_iters=gn_iters, ckpt_every=ckpt, ckpt_tune_ms=[round(x, 3) for x in tune_ms],
         ms_coarse=round(t_coarse * 1e3, 2), ms_topk=round(t_topk * 1e3, 2), ms_gn=round(t_gn * 1e3, 2),
         ms_rescans=round(t_rounds * 1e3, 2), rescan_seeds=int(seeds_scanned),
         events_per_s_gn=ne / t_a, events_per_s_rescan=ne / t_b, speedup=t_b / t_a,

@@ -265,9 +265,16 @@ rkn_status rkn_batch_results(rkn_ctx *ctx, int32_t max_windows, rkn_window *wind
  * order. Outputs follow p->ptr_flags (host or device pointers). */
 
 /* Upload n_seeds seeds ([n][5] host, FP64) and fix their inlier sets. p->precision
- * must be 32; ckpt_every a multiple of 8 in [8, 4096]. */
+ * must be 32; ckpt_every a multiple of 8 in [8, 4096], or 0 to let the checkpoint
+ * tuner pick it: the adjoint sweep (with J^T J) is timed on these seeds for 32, 64,
+ * 128 and 256 steps and the fastest is kept (rkn_refine_info reports it). */
 rkn_status rkn_refine_setup(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, const int32_t *seed_event,
                             const double *seeds5, int32_t ckpt_every);
+
+/* After rkn_refine_setup: the seed count, the checkpoint interval in use and, if it
+ * was tuned, tune_ms[4] = the timed sweeps for 32, 64, 128, 256 steps (else zeros).
+ * Any output may be NULL. */
+rkn_status rkn_refine_info(rkn_ctx *ctx, int64_t *n_seeds, int32_t *ckpt_every, float *tune_ms);
 
 /* Forward pass at seeds5 ([n][5]; NULL keeps the current seeds): resid [n][H]
  * (H = the largest hit count of an uploaded event; per row the event's hits in

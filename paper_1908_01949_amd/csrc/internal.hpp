@@ -165,6 +165,7 @@ struct rkn_ctx {
   rkn_scan_params r_params{};
   int64_t r_n = 0, r_ntiles = 0, r_ntiles6 = 0;
   int r_ckpt = 64, r_nckpt = 0;
+  float r_tune_ms[4] = {0, 0, 0, 0};   // adjoint sweep times of the checkpoint tuner
   rkn::DevBuf r_seeds, r_seeds0, r_trials, r_event, r_tiles, r_tiles6, r_ident, r_base6, r_mask, r_resid,
       r_argmin, r_resid6, r_argmin6, r_phi, r_phi6, r_phicur, r_tape, r_segbuf, r_list, r_grad, r_jtj, r_cgrad,
       r_slab, r_counter, r_tape6, r_segoff, r_segout, r_accept;

@@ -658,6 +658,21 @@ std::vector<Tile> slot_tiles(const std::vector<int32_t>& ev, int T) {
   return tiles;
 }
 
+// Sets the checkpoint interval and sizes the buffers that depend on it.
+hipError_t refine_ckpt_buffers(rkn_ctx* c, int ckpt) {
+  c->r_ckpt = ckpt;
+  c->r_nckpt = (c->r_params.n_steps + ckpt - 1) / ckpt;
+  const size_t n = (size_t)c->r_n, nk = (size_t)c->r_nckpt;
+  hipError_t e;
+  if ((e = c->r_tape.ensure(sizeof(float) * 13 * n * nk)) != hipSuccess ||
+      (e = c->r_tape6.ensure(sizeof(float) * 13 * 6 * n * nk)) != hipSuccess ||
+      (e = c->r_segbuf.ensure(sizeof(float) * 6 * n * (size_t)(ckpt + 1) * nk)) != hipSuccess ||
+      (e = c->r_segoff.ensure(sizeof(int32_t) * n * (nk + 1))) != hipSuccess ||
+      (e = c->r_segout.ensure(sizeof(double) * kSegVals * n * nk)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
 hipError_t refine_forward(rkn_ctx* c, bool trials, int define_mask, bool tape) {
   const int64_t n = c->r_n;
   const int copies = trials ? 6 : 1;
@@ -740,8 +755,8 @@ rkn_status rkn_refine_setup(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seed
     c->err = "refine: need 1..2^24 seeds with events";
     return RKN_E_ARG;
   }
-  if (ckpt_every < 8 || ckpt_every % 8 != 0 || ckpt_every > 4096) {
-    c->err = "refine: ckpt_every must be a multiple of 8 in [8, 4096]";
+  if (ckpt_every != 0 && (ckpt_every < 8 || ckpt_every % 8 != 0 || ckpt_every > 4096)) {
+    c->err = "refine: ckpt_every must be 0 (tuned) or a multiple of 8 in [8, 4096]";
     return RKN_E_ARG;
   }
   for (int64_t s = 0; s < n_seeds; ++s) {
@@ -760,8 +775,9 @@ rkn_status rkn_refine_setup(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seed
   c->r_params = *p;
   c->r_params.block_steps = 8;
   c->r_n = n_seeds;
-  c->r_ckpt = ckpt_every;
-  c->r_nckpt = (p->n_steps + ckpt_every - 1) / ckpt_every;
+  c->r_ckpt = ckpt_every > 0 ? ckpt_every : 64;
+  c->r_nckpt = (p->n_steps + c->r_ckpt - 1) / c->r_ckpt;
+  for (float& t : c->r_tune_ms) t = 0.0f;
   const int H = c->max_hits_event > 0 ? c->max_hits_event : 1;
   const int T = scan_tile(c, &c->r_params);
   std::vector<int32_t> ev(seed_event, seed_event + n_seeds);
@@ -794,11 +810,6 @@ rkn_status rkn_refine_setup(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seed
       (e = c->r_phi.ensure(sizeof(double) * n)) != hipSuccess ||
       (e = c->r_phi6.ensure(sizeof(double) * 6 * n)) != hipSuccess ||
       (e = c->r_phicur.ensure(sizeof(double) * n)) != hipSuccess ||
-      (e = c->r_tape.ensure(sizeof(float) * 13 * n * c->r_nckpt)) != hipSuccess ||
-      (e = c->r_tape6.ensure(sizeof(float) * 13 * 6 * n * c->r_nckpt)) != hipSuccess ||
-      (e = c->r_segbuf.ensure(sizeof(float) * 6 * n * (ckpt_every + 1) * c->r_nckpt)) != hipSuccess ||
-      (e = c->r_segoff.ensure(sizeof(int32_t) * n * (c->r_nckpt + 1))) != hipSuccess ||
-      (e = c->r_segout.ensure(sizeof(double) * kSegVals * n * c->r_nckpt)) != hipSuccess ||
       (e = c->r_list.ensure(sizeof(int2) * n * H)) != hipSuccess ||
       (e = c->r_grad.ensure(sizeof(double) * 5 * n)) != hipSuccess ||
       (e = c->r_jtj.ensure(sizeof(double) * 25 * n)) != hipSuccess ||
@@ -816,11 +827,54 @@ rkn_status rkn_refine_setup(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seed
     e = hipMemcpyAsync(c->r_ident.p, ident.data(), sizeof(int64_t) * 6 * n, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->r_base6.p, base6.data(), sizeof(int64_t) * 6 * n, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return rerr(c, e, "refine setup");
+  // checkpoint interval: given, or the fastest adjoint sweep (with J^T J) among
+  // 32, 64, 128 and 256 steps on these seeds
+  int chosen = c->r_ckpt;
+  if (ckpt_every == 0) {
+    static const int cand[4] = {32, 64, 128, 256};
+    hipEvent_t t0 = nullptr, t1e = nullptr;
+    if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1e)) != hipSuccess)
+      return rerr(c, e, "refine tune");
+    float best = INFINITY;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+      e = refine_ckpt_buffers(c, cand[i]);
+      if (e == hipSuccess) e = refine_forward(c, false, 1, true);
+      if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+      if (e == hipSuccess) e = refine_backward(c, nullptr, true);
+      if (e == hipSuccess) e = hipEventRecord(t1e, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1e);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1e);
+      c->r_tune_ms[i] = ms;
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        chosen = cand[i];
+      }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1e);
+    if (e != hipSuccess) return rerr(c, e, "refine tune");
+  }
   // the inlier sets: classification at the starting seeds
+  e = refine_ckpt_buffers(c, chosen);
   if (e == hipSuccess) e = refine_forward(c, false, 1, true);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return rerr(c, e, "refine setup");
   c->r_ready = true;
+  return RKN_OK;
+}
+
+rkn_status rkn_refine_info(rkn_ctx* c, int64_t* n_seeds, int32_t* ckpt_every, float* tune_ms) {
+  if (!c) return RKN_E_ARG;
+  if (!c->r_ready) {
+    c->err = "refine: nothing set up";
+    return RKN_E_STATE;
+  }
+  if (n_seeds) *n_seeds = c->r_n;
+  if (ckpt_every) *ckpt_every = c->r_ckpt;
+  if (tune_ms)
+    for (int i = 0; i < 4; ++i) tune_ms[i] = c->r_tune_ms[i];
   return RKN_OK;
 }
 

@@ -86,6 +86,7 @@ _SIGS = {
     "rkn_scan_windows_topk": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, _P, _P, _P]),
     "rkn_scan_shape": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_refine_setup": (C.c_int32, [_P, _P, C.c_int64, _P, _P, C.c_int32]),
+    "rkn_refine_info": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_residuals_fwd": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_adjoint_bwd": (C.c_int32, [_P, _P, _P, _P, _P]),
     "rkn_gn_refine": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
@@ -347,6 +348,13 @@ def rkn_refine_setup(ctx, p: rkn_scan_params, seed_event, seeds5, ckpt_every: in
     se = _host(seed_event, np.int32)
     s5 = np.ascontiguousarray(np.asarray(seeds5, np.float64).reshape(-1, 5))
     _check(ctx, load_library().rkn_refine_setup(ctx, C.byref(p), se.size, _ptr(se), _ptr(s5), int(ckpt_every)))
+
+
+def rkn_refine_info(ctx):
+    """(n_seeds, ckpt_every, tune_ms[4]) of the current refinement setup."""
+    n = C.c_int64(); k = C.c_int32(); ms = (C.c_float * 4)()
+    _check(ctx, load_library().rkn_refine_info(ctx, C.byref(n), C.byref(k), ms))
+    return n.value, k.value, list(ms)
 
 
 def rkn_residuals_fwd(ctx, seeds5=None, resid=None, phi=None):
