@@ -83,17 +83,25 @@ def measured_traffic():
     """HBM bytes per scan launch from the committed counter record (FETCH_SIZE and
     WRITE_SIZE runs scaled by a plain copy's counts), or None when the kernel sources
     differ from the ones the counters were taken on."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "scan_kernel_512ev_solenoid_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
+    return int(rec["traffic_bytes"]) if rec.get("kernel_source_sha256") == kernel_source_hash() else None
+
+
+def kernel_source_hash():
+    """SHA-256 of the scan kernel's sources with comments and blank space removed."""
+    import hashlib
     h = hashlib.sha256()
     for fn in ("scan.hip", "device_math.hpp", "internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1908_01949_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
-    return int(rec["traffic_bytes"]) if rec.get("kernel_source_sha256") == h.hexdigest() else None
+        with open(os.path.join(ROOT, "paper_1908_01949_amd", "csrc", fn)) as f:
+            for line in f:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()
 
 
 def _sync_time(fn):

@@ -3,8 +3,9 @@
 // replayed per batch (section 2.1 seeding and section 2.2 scan, many events).
 //
 // Graph A: the Hough stage for all events and the expansion of its window slots
-//          into the compact window list, the seed tiles (<= 256 seeds of one
-//          window) and the per-event tile ranges, all on the device.
+//          into the compact window list, the seed tiles (at most one workgroup's
+//          worth of seeds of one window) and the per-event tile ranges, all on the
+//          device.
 // Graph B: the persistent scan over the tiles (atomic tile queue, tile count read
 //          from device memory) and the per-event argmin.
 // HIP events recorded between the two graph launches time each stage.

@@ -18,24 +18,6 @@ struct alignas(sizeof(R) * 8) HitRec {
   R mx, my, mz, ux, uy, uz, L, drift;
 };
 
-// Wave-uniform read of a hit record through the constant address space, so the
-// compiler issues scalar loads (the records are read-only while a scan runs).
-template <typename R>
-__device__ __forceinline__ HitRec<R> load_hit_uniform(const HitRec<R>* p, int h) {
-  const __attribute__((address_space(4))) HitRec<R>* q =
-      (const __attribute__((address_space(4))) HitRec<R>*)p;
-  HitRec<R> w;
-  w.mx = q[h].mx;
-  w.my = q[h].my;
-  w.mz = q[h].mz;
-  w.ux = q[h].ux;
-  w.uy = q[h].uy;
-  w.uz = q[h].uz;
-  w.L = q[h].L;
-  w.drift = q[h].drift;
-  return w;
-}
-
 // Axisymmetric field: uniform B_z, or FP32 (B_r, B_z) nodes interleaved [nz][nr].
 struct FieldDev {
   const float2* nodes;

@@ -38,8 +38,7 @@ struct DevBuf {
 };
 
 // A tile is up to scan_tile() consecutive seeds of one window (never straddles
-// events); kTile is the largest tile size of any scan configuration.
-constexpr int kTile = 512;
+// events).
 struct Tile {
   int32_t window;
   int32_t event;

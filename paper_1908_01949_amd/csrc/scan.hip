@@ -4,22 +4,24 @@
 //   * one lane per seed; a workgroup of 64*WAVES lanes takes tiles of up to 64*WAVES
 //     seeds of one event from an atomic queue (persistent grid sized to the resident
 //     capacity); with a field map, the 65x129 (B_r, B_z) nodes are staged in LDS once
-//     per workgroup and shared by its 8 waves;
-//   * the event's hits are staged in LDS, ordered by layer, with a 1 mm radial
-//     table that maps a radius range to the range of hits whose layer band (widened
-//     by the largest drift + sqrt(lambda) + 1 mm) it can meet;
+//     per workgroup and shared by all its waves;
+//   * the event's hits are staged in LDS, ordered by layer and, within a layer, by
+//     the twisted azimuth psi = phi - s_l z of the wire centre; a 1 mm radial table
+//     maps a radius range to the layers whose band (widened by the largest drift +
+//     sqrt(lambda) + 1 mm) it can meet, and a layer x psi-sector table gives the
+//     circular run of a layer's hits that a block in that sector can reach;
 //   * each lane runs B RKN steps in registers and writes the B+1 points to an LDS
-//     column; each lane then walks its own hit range (records gathered from LDS),
-//     tests each hit with a sphere bound (all B chords lie within B h / 2 of the
-//     block's middle point) and the wave appends the survivors to an LDS work list
-//     (ballot + mbcnt compaction);
-//   * the list is processed densely: every lane takes one (seed, hit) item, computes
-//     the exact chord/wire distance of the B chords and folds the minimum into the
-//     seed's running minimum (a per-workgroup slab [hit][lane] in HBM, updated with
-//     an integer atomic min on the non-negative float bit pattern: order-free and
+//     column; it then walks the runs of its block's layers and sector (records
+//     gathered from LDS), tests each hit with a sphere bound (all B chords lie within
+//     B h / 2 of the block's middle point) and the wave appends the survivors to an
+//     LDS work list (ballot + mbcnt compaction);
+//   * the list is processed densely (one item per lane, the tail spread over lane
+//     groups): exact chord/wire distance of the B chords, the minimum folded into the
+//     seed's running minimum (a per-workgroup slab [hit][lane] in HBM, updated with an
+//     integer atomic min on the non-negative float bit pattern: order-free and
 //     deterministic);
 //   * after the last block each lane forms E = sum min((D - d)^2, lambda) in FP64.
-// Both culls are exact: a pair they drop can only have a distance above
+// Every filter is exact: a pair it drops can only have a distance above
 // d + sqrt(lambda), where the term is lambda whatever the distance is.
 #include <type_traits>
 
