@@ -35,10 +35,14 @@ def batch_hough_params(field):
     return rk.make_hough_params(b_ref=field.b_ref, **workloads.BATCH["hough"])
 
 
-def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_steps, lam, seconds):
-    """The FP64 oracle timed on this host's cores on a bounded random sample of the
-    same batch; also counts the pruned algorithm's work for the roofline."""
+def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_steps, lam, seconds, block_steps):
+    """The FP64 oracle timed on this host's cores (OpenMP threads) on a bounded random
+    sample of the same batch, and on one thread (the paper's serial CPU) on a smaller
+    sample; also counts the pruned algorithm's work for the roofline with the block
+    size the kernel uses."""
+    import ctypes
     import oracle
+    gomp = ctypes.CDLL("libgomp.so.1")
     O = oracle.Oracle(geo, field)
     prm = O.params(n_steps=n_steps, lambda_mm2=lam)
     off, wid, dr = synth.pack_events(events)
@@ -53,7 +57,7 @@ def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_ste
         seeds = np.array([O.window_seed(windows[kk], gg - wbase[kk]) for kk, gg in zip(k, g)])
         return g, windows["event"][k].astype(np.int32), seeds
 
-    cores = os.cpu_count() or 1
+    cores = int(gomp.omp_get_max_threads())
     g, se, seeds = draw(min(64, total))
     t = time.perf_counter()
     sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1)
@@ -65,17 +69,26 @@ def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_ste
         sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1)
         dt = time.perf_counter() - t
     rel = float(np.max(np.abs(gpu_scores[g] - sc) / np.maximum(np.abs(sc), 1e-12)))
+    # one thread, on the first seeds of the sample (about a quarter of the time budget)
+    m1 = max(4, min(len(g), int(len(g) * 0.25 / max(cores, 1))))
+    gomp.omp_set_num_threads(1)
+    t = time.perf_counter()
+    O.scan_seeds(prm, off, wid, dr, se[:m1], seeds[:m1], mode=1)
+    dt1 = time.perf_counter() - t
+    gomp.omp_set_num_threads(cores)
     # pruned-algorithm work counts on a sub-sample
     cull = pairs = 0
     m = min(64, len(g))
     for i in range(m):
         e = int(se[i])
-        _, _, cu, pk = O.score_blocked(prm, seeds[i], wid[off[e]:off[e + 1]], dr[off[e]:off[e + 1]], 8)
+        _, _, cu, pk = O.score_blocked(prm, seeds[i], wid[off[e]:off[e + 1]], dr[off[e]:off[e + 1]], block_steps)
         cull += cu; pairs += pk
     ss = m * n_steps
     return dict(value=len(g) * n_steps / dt, unit="seed-steps/s", cores=cores, kind="oracle",
                 sample=f"{len(g)} seeds drawn uniformly from the {total} of the batch, {n_steps} steps each, "
-                       f"FP64 band-pruned oracle, OpenMP over seeds, {dt:.1f} s"), \
+                       f"FP64 band-pruned oracle, OpenMP over seeds, {dt:.1f} s",
+                value_1_thread=m1 * n_steps / dt1,
+                sample_1_thread=f"the first {m1} seeds of that sample on one thread, {dt1:.1f} s"), \
         dict(cull_per_step=cull / ss, pairs_per_step=pairs / ss, sample_max_rel_score_err=rel)
 
 
@@ -238,6 +251,56 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
         rule=f"rescans stop per event when Phi <= (1+{rtol:g}) Phi_GN on the GN inlier set, <= {max_rounds} rounds")
 
 
+def other_workloads(geo, reps=3):
+    """The single-event workloads, timed on the GPU (device outputs, inputs resident):
+    a 6^5 FP64 scan of a single-turn event, a 16^5 FP32 scan of a multi-turn event
+    (both uniform 1 T) and the Hough windows (12^5 per candidate) of a 150-hit event
+    in the solenoid map."""
+    import torch
+    out = {}
+    uf, sf = synth.uniform_field(1.0), synth.solenoid_field()
+    cases = []
+    ev1 = synth.event_single_turn(geo, uf, 0)
+    wl = workloads.SINGLE_TURN
+    cases.append(("single_turn_6^5_fp64", uf, ev1, wl, synth.make_windows(
+        [(0, 0, ev1.truth_seeds[0], wl["half_width"], [wl["count"]] * 5)])))
+    ev2 = synth.event_multi_turn(geo, uf, 0)
+    wl = workloads.MULTI_TURN
+    cases.append(("multi_turn_16^5_fp32", uf, ev2, wl, synth.make_windows(
+        [(0, 0, ev2.truth_seeds[0], wl["half_width"], [wl["count"]] * 5)])))
+    ev3 = synth.event_fixed_total(geo, sf, 0, n_total=150, noise_frac=0.2)
+    cases.append(("hough_event_12^5_fp32", sf, ev3, workloads.HOUGH_EVENT, None))
+    for name, field, ev, wl, w in cases:
+        off, wid, dr = synth.pack_events([ev])
+        c = rk.Context(0)
+        c.upload_geometry(geo); c.upload_field(field); c.upload_hits(off, wid, dr)
+        t_hough = 0.0
+        if w is None:
+            hp = rk.make_hough_params(b_ref=field.b_ref, **wl["hough"])
+            w = rk.rkn_hough_seed_windows(c.ctx, hp)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                rk.rkn_hough_seed_windows(c.ctx, hp)
+            t_hough = (time.perf_counter() - t) / reps
+        n = int(np.prod(w["count"].astype(np.int64), axis=1).sum())
+        p = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"], ptr_flags=rk.RKN_PTR_DEVICE)
+        score = torch.empty(n, dtype=torch.float64, device="cuda")
+        bi = torch.empty(1, dtype=torch.int64, device="cuda"); bs = torch.empty(1, dtype=torch.float64, device="cuda")
+        rk.rkn_scan_windows(c.ctx, p, w, score, None, bi, bs)
+        rk.rkn_synchronize(c.ctx)
+        t = time.perf_counter()
+        for _ in range(reps):
+            rk.rkn_scan_windows(c.ctx, p, w, score, None, bi, bs)
+        rk.rkn_synchronize(c.ctx)
+        dt = (time.perf_counter() - t) / reps
+        out[name] = dict(seeds=n, steps=wl["n_steps"], ms_scan=round(dt * 1e3, 3),
+                         seed_steps_per_s=n * wl["n_steps"] / dt, hough_ms=round(t_hough * 1e3, 3) or None)
+        log(f"{name}: {out[name]}")
+        c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +311,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement comparison")
+    ap.add_argument("--no-other", action="store_true", help="skip the single-event workloads")
     ap.add_argument("--block-steps", type=int, default=0, help="RKN steps per cull block (0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
@@ -310,7 +374,7 @@ def main():
     if not args.no_cpu_baseline:
         windows, scores, _, ev_seed_off = rk.rkn_batch_results(ctx.ctx, ne)
         cpu, work = cpu_baseline_leg(geo, field, events, windows, ev_seed_off, scores, args.rkn_steps,
-                                     lam, args.cpu_seconds)
+                                     lam, args.cpu_seconds, bsteps)
         log(f"cpu baseline: {cpu}")
         log(f"work counts: {work}")
     roof = None
@@ -341,6 +405,8 @@ def main():
         out["refine"] = refine_leg(ctx, sp, ne, dt / args.steps)
         log(f"refine: {out['refine']}")
     ctx.close()
+    if not args.no_other:
+        out["other_workloads"] = other_workloads(geo)
     print(json.dumps(out))
 
 
