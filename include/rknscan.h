@@ -252,6 +252,30 @@ rkn_status rkn_batch_info(rkn_ctx *ctx, int32_t *n_windows, int64_t *n_seeds, fl
 rkn_status rkn_batch_results(rkn_ctx *ctx, int32_t max_windows, rkn_window *windows, int32_t *n_windows,
                              int64_t max_seeds, double *score, int32_t *n_in, int64_t *ev_seed_off);
 
+/* ---- Hit classification and the two-direction quality count -----------------------
+ * Section 2.2: a hit belongs to a seed's track when (D - d)^2 < lambda; the scan is
+ * run independently from seed sets at the chamber entrance and at its exit, and a
+ * track is kept when the number N_c of hits both directions classify to it reaches a
+ * threshold (20 in the paper). The exit-side scan is the time-reversed track: seeds at
+ * the exit crossing with reversed momentum, propagated with the opposite charge
+ * (rkn_hough_seed_windows and the scans produce them when given that charge). FP32
+ * propagation (p->precision is ignored); masks are [n][H] bytes (H = the largest hit
+ * count of an uploaded event; per row the event's hits in upload order, 0 past them);
+ * outputs follow p->ptr_flags. */
+
+/* Per seed (any event order): mask [n][H] of the hits classified to its track (may
+ * be NULL) and n_in [n] their count (may be NULL; not both). */
+rkn_status rkn_classify_hits(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, const int32_t *seed_event,
+                             const double *seeds5, uint8_t *mask, int32_t *n_in);
+
+/* Per pair (event pair_event[i], entrance seed seeds_entry5[i] propagated with
+ * p->charge, exit seed seeds_exit5[i] propagated with -p->charge): the two masks
+ * (either may be NULL) and n_common [n] = the number of hits in both. */
+rkn_status rkn_bidirectional_common(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_pairs,
+                                    const int32_t *pair_event, const double *seeds_entry5,
+                                    const double *seeds_exit5, uint8_t *mask_entry, uint8_t *mask_exit,
+                                    int32_t *n_common);
+
 /* ---- Differentiated refinement of seeds --------------------------------------------
  * The paper refines the best seeds by rescanning finer grids (section 2.2); this is
  * the derivative-based alternative. Per seed the objective is

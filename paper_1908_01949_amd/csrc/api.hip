@@ -134,7 +134,9 @@ void rkn_destroy(rkn_ctx* c) {
                     &c->out_best_i, &c->out_best_e, &c->trace_buf, &c->seeds_buf, &c->perm_buf,
                     &c->wire_wx, &c->wire_wy, &c->hits_wire, &c->hough_acc, &c->hough_max,
                     &c->hough_cand_n, &c->hough_cand, &c->hough_slots, &c->hough_nsel, &c->hits_orig, &c->hits_phi, &c->layer_ext,
-                    &c->sel_seg, &c->sel_win, &c->sel_idx, &c->sel_sc, &c->sel_seed};
+                    &c->sel_seg, &c->sel_win, &c->sel_idx, &c->sel_sc, &c->sel_seed, &c->cl_seeds,
+                    &c->cl_perm, &c->cl_tiles, &c->cl_resid, &c->cl_argmin, &c->cl_phi, &c->cl_mask,
+                    &c->cl_count};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->extra) b.release();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);

@@ -140,6 +140,7 @@ struct rkn_ctx {
   rkn::DevBuf windows, tiles, ev_tiles, parts, counter, mscratch, out_score, out_nin, out_best_i,
       out_best_e, trace_buf, seeds_buf, perm_buf;
   rkn::DevBuf sel_seg, sel_win, sel_idx, sel_sc, sel_seed;   // per-event top-k selection
+  rkn::DevBuf cl_seeds, cl_perm, cl_tiles, cl_resid, cl_argmin, cl_phi, cl_mask, cl_count;   // classification
   std::vector<rkn::DevBuf> extra;
 
   // batched path (planned once, launched as captured graphs)

@@ -85,6 +85,8 @@ _SIGS = {
     "rkn_batch_autotune": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     "rkn_scan_windows_topk": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, _P, _P, _P]),
     "rkn_scan_shape": (C.c_int32, [_P, _P, _P, _P]),
+    "rkn_classify_hits": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P]),
+    "rkn_bidirectional_common": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P]),
     "rkn_refine_setup": (C.c_int32, [_P, _P, C.c_int64, _P, _P, C.c_int32]),
     "rkn_refine_info": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_residuals_fwd": (C.c_int32, [_P, _P, _P, _P]),
@@ -342,6 +344,33 @@ def rkn_batch_results(ctx, n_events: int, want_scores: bool = True):
                                                  _ptr(off)))
     return windows_from_c(arr, n.value), (score[:ns] if want_scores else None), \
         (nin[:ns] if want_scores else None), off
+
+
+def rkn_classify_hits(ctx, p: rkn_scan_params, seed_event, seeds5, n_hits_max, mask=None, n_in=None):
+    """Inlier masks [n][H] (uint8) and counts [n] of explicit seeds (host arrays if None)."""
+    se = _host(seed_event, np.int32)
+    s5 = np.ascontiguousarray(np.asarray(seeds5, np.float64).reshape(-1, 5))
+    if mask is None and n_in is None:
+        mask = np.zeros((se.size, n_hits_max), np.uint8)
+        n_in = np.zeros(se.size, np.int32)
+    _check(ctx, load_library().rkn_classify_hits(ctx, C.byref(p), se.size, _ptr(se), _ptr(s5), _ptr(mask),
+                                                 _ptr(n_in)))
+    return mask, n_in
+
+
+def rkn_bidirectional_common(ctx, p: rkn_scan_params, pair_event, seeds_entry5, seeds_exit5, n_hits_max,
+                             mask_entry=None, mask_exit=None, n_common=None):
+    """Per pair: the entrance and exit masks and the number of hits in both."""
+    se = _host(pair_event, np.int32)
+    a = np.ascontiguousarray(np.asarray(seeds_entry5, np.float64).reshape(-1, 5))
+    b = np.ascontiguousarray(np.asarray(seeds_exit5, np.float64).reshape(-1, 5))
+    if n_common is None:
+        mask_entry = np.zeros((se.size, n_hits_max), np.uint8)
+        mask_exit = np.zeros((se.size, n_hits_max), np.uint8)
+        n_common = np.zeros(se.size, np.int32)
+    _check(ctx, load_library().rkn_bidirectional_common(ctx, C.byref(p), se.size, _ptr(se), _ptr(a), _ptr(b),
+                                                        _ptr(mask_entry), _ptr(mask_exit), _ptr(n_common)))
+    return mask_entry, mask_exit, n_common
 
 
 def rkn_refine_setup(ctx, p: rkn_scan_params, seed_event, seeds5, ckpt_every: int = 64) -> None:
