@@ -251,6 +251,33 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
         rule=f"rescans stop per event when Phi <= (1+{rtol:g}) Phi_GN on the GN inlier set, <= {max_rounds} rounds")
 
 
+def bidirectional_leg(ctx, field, sp, n_events, t_entrance, n_hits_max, n_c_min=20):
+    """Section 2.2's two-direction scan: the batch is scanned again from seed sets at the
+    chamber exit (the time-reversed track: the circle Hough stage and the scan with the
+    opposite charge), and each event's best entrance and exit seeds classify its hits;
+    the event is kept when at least n_c_min hits are classified from both sides."""
+    ne = n_events
+    ent_idx, _, ent_s5 = rk.rkn_batch_topk(ctx.ctx, 1, n_events=ne)
+    hp_exit = rk.make_hough_params(b_ref=field.b_ref, charge=-sp.charge, **workloads.BATCH["hough"])
+    sp_exit = rk.make_scan_params(n_steps=sp.n_steps, precision=sp.precision, lambda_mm2=sp.lambda_mm2,
+                                  charge=-sp.charge, block_steps=sp.block_steps)
+    rk.rkn_batch_plan(ctx.ctx, hp_exit, sp_exit)
+    rk.rkn_batch_launch(ctx.ctx, None, None)
+    _, t_exit = _sync_time(lambda: rk.rkn_batch_launch(ctx.ctx, None, None))
+    ext_idx, _, ext_s5 = rk.rkn_batch_topk(ctx.ctx, 1, n_events=ne)
+    both = (ent_idx[:, 0] >= 0) & (ext_idx[:, 0] >= 0)
+    ev = np.nonzero(both)[0].astype(np.int32)
+    (_, _, n_common), t_cls = _sync_time(lambda: rk.rkn_bidirectional_common(
+        ctx.ctx, sp, ev, ent_s5[ev, 0], ext_s5[ev, 0], n_hits_max))
+    kept = int((n_common >= n_c_min).sum())
+    t_all = t_entrance + t_exit + t_cls
+    log(f"bidirectional: exit scan {t_exit * 1e3:.1f} ms, classification {t_cls * 1e3:.1f} ms, "
+        f"{kept} of {ev.size} events with N_c >= {n_c_min}")
+    return dict(ms_entrance=round(t_entrance * 1e3, 2), ms_exit=round(t_exit * 1e3, 2),
+                ms_classify=round(t_cls * 1e3, 2), events_per_s=ne / t_all, events_with_both=int(ev.size),
+                events_kept=kept, n_c_min=n_c_min, n_c_mean=float(n_common.mean()) if ev.size else 0.0)
+
+
 def other_workloads(geo, reps=3):
     """The single-event workloads, timed on the GPU (device outputs, inputs resident):
     a 6^5 FP64 scan of a single-turn event, a 16^5 FP32 scan of a multi-turn event
@@ -312,6 +339,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement comparison")
     ap.add_argument("--no-other", action="store_true", help="skip the single-event workloads")
+    ap.add_argument("--no-bidir", action="store_true", help="skip the two-direction scan")
     ap.add_argument("--block-steps", type=int, default=0, help="RKN steps per cull block (0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
@@ -404,6 +432,8 @@ def main():
     if not args.no_refine:
         out["refine"] = refine_leg(ctx, sp, ne, dt / args.steps)
         log(f"refine: {out['refine']}")
+    if not args.no_bidir:
+        out["bidirectional"] = bidirectional_leg(ctx, field, sp, ne, dt / args.steps, int(np.diff(off).max()))
     ctx.close()
     if not args.no_other:
         out["other_workloads"] = other_workloads(geo)
