@@ -43,7 +43,7 @@ class OrcField(C.Structure):
 
 class OrcParams(C.Structure):
     _fields_ = [("R0", C.c_double), ("charge", C.c_double), ("step_mm", C.c_double),
-                ("lambda_mm2", C.c_double), ("n_steps", C.c_int32), ("pad", C.c_int32)]
+                ("lambda_mm2", C.c_double), ("n_steps", C.c_int32), ("turn_stop", C.c_int32)]
 
 
 class OrcWindow(C.Structure):
@@ -93,6 +93,7 @@ def lib():
         _lib.orc_hough_peaks.argtypes = [P, P, C.c_int32, P, P]
         _lib.orc_hough_window.argtypes = [P, P, C.c_int64, P]
         _lib.orc_hough_seed_windows.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P]
+        _lib.orc_neighbour_seed.argtypes = [P, P, P, C.c_int32, C.c_int32, P]
     return _lib
 
 
@@ -121,8 +122,8 @@ class Oracle:
                                   _ptr(arr(field.br_grid, np.float32)), _ptr(arr(field.bz_grid, np.float32)))
 
     @staticmethod
-    def params(R0=500.0, charge=-1.0, step_mm=1.0, lambda_mm2=64.0, n_steps=2000) -> OrcParams:
-        return OrcParams(R0, charge, step_mm, lambda_mm2, n_steps, 0)
+    def params(R0=500.0, charge=-1.0, step_mm=1.0, lambda_mm2=64.0, n_steps=2000, turn_stop=0) -> OrcParams:
+        return OrcParams(R0, charge, step_mm, lambda_mm2, n_steps, int(turn_stop))
 
     # ---- propagation -------------------------------------------------------------
     def field_eval(self, x):
@@ -147,6 +148,13 @@ class Oracle:
         lib().orc_trace(C.byref(self.field), C.byref(prm), seeds5.shape[0], _ptr(seeds5),
                         step_idx.size, _ptr(step_idx), _ptr(out))
         return out
+
+    def neighbour_seed(self, prm, seed, direction, max_steps=6000):
+        """Seed of the neighbouring turn partition (direction +1 next, -1 previous), or None."""
+        s = np.ascontiguousarray(seed, np.float64); out = np.zeros(5)
+        ok = lib().orc_neighbour_seed(C.byref(self.field), C.byref(prm), _ptr(s), int(direction), int(max_steps),
+                                      _ptr(out))
+        return out if ok else None
 
     # ---- distances and score -----------------------------------------------------
     @staticmethod

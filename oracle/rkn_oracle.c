@@ -112,21 +112,30 @@ void orc_rkn_step(const orc_field *f, double Lam, double h, double x[3], double 
   }
 }
 
+/* Section 2.3 and section 4.2 (the propagation runs to the end of the turn
+ * partition). Reading: with turn_stop set, the partition ends with the first step
+ * whose end point lies inside the seed cylinder r < R0 (the track has left the
+ * chamber inwards); that step's chord is the last one. */
+static int turn_ended(const orc_params *p, const double x[3]) {
+  return p->turn_stop && x[0] * x[0] + x[1] * x[1] < p->R0 * p->R0;
+}
+
 int orc_trace(const orc_field *f, const orc_params *p, int64_t n_seeds, const double *seeds5,
               int32_t n_sel, const int32_t *step_idx, double *states) {
   int64_t s;
   for (s = 0; s < n_seeds; ++s) {
     double x[3], T[3], Lam;
     double *out = states + s * (int64_t)n_sel * 6;
-    int32_t k, n = 0;
+    int32_t k, n = 0, ended = 0;
     if (!orc_seed_state(p, seeds5 + 5 * s, x, T, &Lam)) {
       for (k = 0; k < 6 * n_sel; ++k) out[k] = NAN;
       continue;
     }
     for (k = 0; k < n_sel; ++k) {
-      while (n < step_idx[k]) {
+      while (n < step_idx[k] && !ended) {
         orc_rkn_step(f, Lam, p->step_mm, x, T);
         ++n;
+        ended = turn_ended(p, x);
       }
       out[6 * k + 0] = x[0]; out[6 * k + 1] = x[1]; out[6 * k + 2] = x[2];
       out[6 * k + 3] = T[0]; out[6 * k + 4] = T[1]; out[6 * k + 5] = T[2];
@@ -225,6 +234,7 @@ int orc_doca2(const orc_geometry *g, const orc_field *f, const orc_params *p, co
       v = orc_seg_wire_dist2(xo, x, m, u, L);
       if (v < d2[i]) d2[i] = v;
     }
+    if (turn_ended(p, x)) break;
   }
   return 1;
 }
@@ -285,6 +295,7 @@ double orc_score(const orc_geometry *g, const orc_field *f, const orc_params *p,
       ++np;
       if (v < d2[i]) d2[i] = v;
     }
+    if (turn_ended(p, x)) break;
   }
   for (i = 0; i < n_hits; ++i) {
     double r = sqrt(d2[i]) - (double)drift[i];
@@ -319,7 +330,7 @@ double orc_score_blocked(const orc_geometry *g, const orc_field *f, const orc_pa
   double (*pts)[3] = (double (*)[3])malloc(sizeof(double) * 3 * (B + 1));
   double sl = sqrt(p->lambda_mm2), h = p->step_mm;
   int64_t nc = 0, np = 0;
-  int32_t i, n, j, cnt = 0;
+  int32_t i, n, j, cnt = 0, ended = 0;
   for (i = 0; i < n_hits; ++i) {
     d2[i] = INFINITY;
     if ((double)drift[i] > dmax) dmax = (double)drift[i];
@@ -332,13 +343,18 @@ double orc_score_blocked(const orc_geometry *g, const orc_field *f, const orc_pa
     if (pairs) *pairs = 0;
     return INFINITY;
   }
-  for (n = 0; n < p->n_steps; n += B) {
+  for (n = 0; n < p->n_steps && !ended; n += B) {
     int nb = p->n_steps - n < B ? p->n_steps - n : B;
     double rmin = INFINITY, rmax = 0.0, D = dmax + sl + 1.0;
     const double *c;
     pts[0][0] = x[0]; pts[0][1] = x[1]; pts[0][2] = x[2];
+    /* after the end of a turn partition the block's remaining points stay at the
+     * last one (zero-length chords, which cannot lower any distance) */
     for (j = 1; j <= nb; ++j) {
-      orc_rkn_step(f, Lam, h, x, T);
+      if (!ended) {
+        orc_rkn_step(f, Lam, h, x, T);
+        ended = turn_ended(p, x);
+      }
       pts[j][0] = x[0]; pts[j][1] = x[1]; pts[j][2] = x[2];
     }
     for (j = 0; j <= nb; ++j) {
@@ -915,6 +931,7 @@ int orc_residual_jacobian(const orc_geometry *g, const orc_field *f, const orc_p
         }
       }
     }
+    if (turn_ended(p, x)) break;
   }
   free(d2);
   return 1;
@@ -1019,5 +1036,65 @@ int orc_gn_refine(const orc_geometry *g, const orc_field *f, const orc_params *p
   }
   phi[iters] = cur;
   free(r); free(J); free(rt); free(Jt);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 2.3: the seed of the neighbouring turn partition, predicted by
+ * extrapolating the fitted track. Reading: the turn partitions of one track meet
+ * r = R0 at their entrances and exits; from an entrance seed the next entrance is the
+ * second crossing of r = R0 after the first step (exit, then re-entry), and the
+ * previous one is the same along the time-reversed track (T and the charge, so
+ * Lambda, reversed). The crossing inside the last step is located by bisection on
+ * the length of a partial step from the state before it; the momentum keeps |p0|. */
+static double radius_minus(const double x[3], double R0) { return sqrt(x[0] * x[0] + x[1] * x[1]) - R0; }
+
+int orc_neighbour_seed(const orc_field *f, const orc_params *p, const double seed[5], int32_t dir,
+                       int32_t max_steps, double out[5]) {
+  double x[3], T[3], Lam, pm, xo[3], To[3];
+  int32_t n, c, side = 0, changes = 0;
+  if (!orc_seed_state(p, seed, x, T, &Lam)) return 0;
+  pm = sqrt(seed[2] * seed[2] + seed[3] * seed[3] + seed[4] * seed[4]);
+  if (dir < 0) {
+    for (c = 0; c < 3; ++c) T[c] = -T[c];
+    Lam = -Lam;
+  }
+  for (n = 0; n < max_steps; ++n) {
+    int in;
+    for (c = 0; c < 3; ++c) { xo[c] = x[c]; To[c] = T[c]; }
+    orc_rkn_step(f, Lam, p->step_mm, x, T);
+    in = radius_minus(x, p->R0) < 0.0;
+    if (n == 0) {
+      side = in;
+      continue;
+    }
+    if (in == side) continue;
+    side = in;
+    if (++changes < 2) continue;
+    {
+      /* g(s) = r(state after a partial step s from (xo, To)) - R0 changes sign on
+       * [0, h]; bisect it */
+      double lo = 0.0, hi = p->step_mm, glo = radius_minus(xo, p->R0), xs[3], Ts[3];
+      int it;
+      for (it = 0; it < 80; ++it) {
+        double mid = 0.5 * (lo + hi), g;
+        for (c = 0; c < 3; ++c) { xs[c] = xo[c]; Ts[c] = To[c]; }
+        orc_rkn_step(f, Lam, mid, xs, Ts);
+        g = radius_minus(xs, p->R0);
+        if ((g < 0.0) == (glo < 0.0)) {
+          lo = mid;
+          glo = g;
+        } else {
+          hi = mid;
+        }
+      }
+      for (c = 0; c < 3; ++c) { xs[c] = xo[c]; Ts[c] = To[c]; }
+      orc_rkn_step(f, Lam, 0.5 * (lo + hi), xs, Ts);
+      out[0] = atan2(xs[1], xs[0]);
+      out[1] = xs[2];
+      for (c = 0; c < 3; ++c) out[2 + c] = (dir < 0 ? -pm : pm) * Ts[c];
+      return 1;
+    }
+  }
   return 0;
 }

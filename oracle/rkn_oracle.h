@@ -40,7 +40,7 @@ typedef struct {
 typedef struct {
   double R0, charge, step_mm, lambda_mm2;
   int32_t n_steps;
-  int32_t pad;
+  int32_t turn_stop;                  /* 1: the track ends with the first step inside r < R0 */
 } orc_params;
 
 typedef struct {
@@ -60,7 +60,8 @@ int orc_seed_state(const orc_params *p, const double seed[5], double x[3], doubl
 /* Section 2.2 (RKN propagation): one Runge-Kutta-Nystrom step of x'' = Lam x' x B(x). */
 void orc_rkn_step(const orc_field *f, double Lam, double h, double x[3], double T[3]);
 
-/* States (x, T) after each of the n_sel step indices (0 = the seed state). */
+/* States (x, T) after each of the n_sel step indices (0 = the seed state); with
+ * turn_stop, a step index beyond the end of the turn partition gives the last state. */
 int orc_trace(const orc_field *f, const orc_params *p, int64_t n_seeds, const double *seeds5,
               int32_t n_sel, const int32_t *step_idx, double *states /* [n][n_sel][6] */);
 
@@ -141,6 +142,16 @@ int orc_residual_jacobian(const orc_geometry *g, const orc_field *f, const orc_p
 int orc_gn_refine(const orc_geometry *g, const orc_field *f, const orc_params *p, int32_t n_hits,
                   const int32_t *wire_id, const float *drift, const double scale[5], int32_t iters,
                   double seed[5], uint8_t *mask, double *phi /* [iters+1] */);
+
+/* ---- Turn partitions (section 2.3) ---- */
+/* Prediction of the neighbouring turn partition's seed by extrapolating a fitted
+ * track: dir = +1 forward from the seed (through its exit and the inner region to the
+ * next entrance), dir = -1 along the time-reversed track (momentum and charge
+ * reversed) back to the previous entrance. The seed is taken where the track crosses
+ * r = R0 for the second time after the first step. Returns 1 and out[5], or 0 if the
+ * crossing is not reached within max_steps or |p| is too small. */
+int orc_neighbour_seed(const orc_field *f, const orc_params *p, const double seed[5], int32_t dir,
+                       int32_t max_steps, double out[5]);
 
 #ifdef __cplusplus
 }

@@ -495,6 +495,17 @@ class Event:
     true_dist: np.ndarray         # float64 [H], true DOCA (nan for noise)
     truth_seeds: np.ndarray       # [n_tracks, 5]
     truth_p: np.ndarray           # [n_tracks]
+    turn_of: np.ndarray | None = None  # int32 [H]: chamber pass of the hit (0 = first), -1 noise
+
+
+def turn_index(tr: "Trajectory", s_hit: np.ndarray) -> np.ndarray:
+    """Truth turn partition of points at arc lengths s_hit: the number of outward
+    crossings of r = R0 after the seed crossing that precede them (0 = first pass)."""
+    r2 = tr.x[:, 0] ** 2 + tr.x[:, 1] ** 2
+    up = (r2[:-1] < R0_SEED ** 2) & (r2[1:] >= R0_SEED ** 2)
+    s_cross = tr.s[1:][up]
+    s_cross = s_cross[s_cross > 1.0]
+    return np.searchsorted(s_cross, np.asarray(s_hit, np.float64), side="right").astype(np.int32)
 
 
 def _draw_vertex(rng, k):
@@ -510,7 +521,7 @@ def _isotropic(rng, k, p):
     return np.stack([s * np.cos(ph), s * np.sin(ph), c], -1) * np.asarray(p)[..., None]
 
 
-def _finish_event(rng, geo, wires, dists, track_of, truths, ps, n_noise, sigma, dmax=8.0):
+def _finish_event(rng, geo, wires, dists, track_of, truths, ps, n_noise, sigma, dmax=8.0, turn_of=None):
     hit_set = set(int(w) for w in wires)
     free = np.array([w for w in range(geo.n_wires) if w not in hit_set], dtype=np.int32)
     noise = rng.choice(free, size=n_noise, replace=False) if n_noise > 0 else np.zeros(0, np.int32)
@@ -523,8 +534,11 @@ def _finish_event(rng, geo, wires, dists, track_of, truths, ps, n_noise, sigma, 
     tro = np.concatenate([np.asarray(track_of, np.int32), np.full(n_noise, -1, np.int32)])
     tdist = np.concatenate([np.asarray(dists, np.float64), np.full(n_noise, np.nan)])
     order = np.argsort(wid, kind="stable")      # hits arrive ordered by wire id
+    turns = None
+    if turn_of is not None:
+        turns = np.concatenate([np.asarray(turn_of, np.int32), np.full(n_noise, -1, np.int32)])[order]
     return Event(wid[order], drift[order], isn[order], tro[order], tdist[order],
-                 np.asarray(truths, np.float64).reshape(-1, 5), np.asarray(ps, np.float64))
+                 np.asarray(truths, np.float64).reshape(-1, 5), np.asarray(ps, np.float64), turns)
 
 
 def event_single_turn(geo: Geometry, field: Field, seed: int, n_hits: int = 40,
@@ -541,8 +555,9 @@ def event_single_turn(geo: Geometry, field: Field, seed: int, n_hits: int = 40,
                 continue
             w, d, s = true_wire_distances(geo, tr, min(turn, n_steps - 20.0))
             if w.size >= n_hits:
-                w, d = w[:n_hits], d[:n_hits]
-                return _finish_event(rng, geo, w, d, np.zeros(n_hits), [tr.seed], [p], 0, sigma)
+                w, d, s = w[:n_hits], d[:n_hits], s[:n_hits]
+                return _finish_event(rng, geo, w, d, np.zeros(n_hits), [tr.seed], [p], 0, sigma,
+                                     turn_of=turn_index(tr, s))
 
 
 def event_multi_turn(geo: Geometry, field: Field, seed: int, n_steps: int = 6000,
@@ -567,7 +582,8 @@ def event_multi_turn(geo: Geometry, field: Field, seed: int, n_steps: int = 6000
             passes = int(np.sum((r[:-1] < geo.layer_rmin[0]) & (r[1:] >= geo.layer_rmin[0])))
             if true_range[0] <= w.size <= true_range[1] and passes >= min_passes:
                 n_noise = int(round(noise_frac * w.size))
-                return _finish_event(rng, geo, w, d, np.zeros(w.size), [tr.seed], [p], n_noise, sigma)
+                return _finish_event(rng, geo, w, d, np.zeros(w.size), [tr.seed], [p], n_noise, sigma,
+                                     turn_of=turn_index(tr, s))
 
 
 def event_fixed_total(geo: Geometry, field: Field, seed: int, n_total: int = 150,
@@ -591,7 +607,7 @@ def event_fixed_total(geo: Geometry, field: Field, seed: int, n_total: int = 150
             w, d, s = true_wire_distances(geo, tr, n_steps - 20.0)
             if w.size >= n_true:
                 return _finish_event(rng, geo, w[:n_true], d[:n_true], np.zeros(n_true),
-                                     [tr.seed], [p], n_noise, sigma)
+                                     [tr.seed], [p], n_noise, sigma, turn_of=turn_index(tr, s[:n_true]))
 
 
 def events_batch(geo: Geometry, field: Field, n_events: int = 512, seed: int = 0,
