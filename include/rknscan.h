@@ -161,6 +161,10 @@ typedef struct {
   int32_t ptr_flags;  /* RKN_PTR_DEVICE: outputs are device pointers               */
   int32_t block_steps;/* 0 (= 8), 4, 6 or 8: RKN steps per cull/DCA block; with the  */
                       /* FP32 field map it also sets the workgroup (16/12/8 waves) */
+  int32_t turn_stop;  /* 0: all n_steps run; 1: the track ends with its turn       */
+                      /* partition (sections 2.3, 4.2): at the first step whose    */
+                      /* end point lies inside r < R0, that step's chord the last  */
+  int32_t reserved;   /* 0                                                         */
 } rkn_scan_params;
 
 /* Score every seed of the windows: E = sum over the event's hits of
@@ -275,6 +279,70 @@ rkn_status rkn_bidirectional_common(rkn_ctx *ctx, const rkn_scan_params *p, int6
                                     const int32_t *pair_event, const double *seeds_entry5,
                                     const double *seeds_exit5, uint8_t *mask_entry, uint8_t *mask_exit,
                                     int32_t *n_common);
+
+/* ---- Turn partitions (section 2.3, full event reconstruction) ----------------------
+ * A turn partition is one pass of a track through the chamber, from its entrance
+ * (the outward crossing of r = R0) to the first step inside r < R0 (the turn_stop
+ * rule of rkn_scan_params). The seed of the neighbouring partition is predicted by
+ * extrapolating a fitted track, and the partitions of an event are found one after
+ * the other, each removing the hits it classifies. */
+
+/* Seeds of the neighbouring turn partitions of n_seeds entrance seeds ([n][5] host,
+ * FP64): direction +1 the next partition (the track propagated forward through its
+ * exit and the inner region to the next outward crossing of r = R0), -1 the previous
+ * one (the same along the time-reversed track: direction and charge reversed). The
+ * seed is taken at the second crossing of r = R0 after the first step, located by
+ * bisection on a partial step's length, with |p| kept. FP64 propagation in the
+ * uploaded field. out5 [n][5] (NaN where not found) and found [n] (1/0: reached
+ * within max_steps), host or device per p->ptr_flags. */
+rkn_status rkn_neighbour_seeds(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, const double *seeds5,
+                               int32_t direction, int32_t max_steps, double *out5, int32_t *found);
+
+#define RKN_TURNS_MAX 16
+
+typedef struct {
+  double half_width[5];       /* window half-widths around a predicted seed             */
+  int32_t count[5];           /* its grid counts (at most 4e6 seeds)                    */
+  int32_t gn_iters;           /* Gauss-Newton iterations per fit (0: no fits)           */
+  double gn_scale[5];         /* Gauss-Newton variable scales (as rkn_gn_refine)        */
+  double lambda_classify_mm2; /* the fine cutoff: second fit, choice and classification */
+  double fine_half_width[2];  /* first partition: (z0, pz0) rescan half-widths          */
+  int32_t fine_count[2];      /* and counts (1, 1: no rescan; at most 1e6 seeds)        */
+  int32_t n_candidates;       /* first partition: lowest-E seeds fitted, 1..RKN_TOPK_MAX */
+  int32_t min_hits;           /* the loop stops below this many unclassified hits, and  */
+                              /* a partition must classify at least this many (10)     */
+  int32_t max_turns;          /* partitions per event, 1..RKN_TURNS_MAX                  */
+  int32_t max_extrap_steps;   /* step limit of each prediction                           */
+} rkn_turn_params;
+
+/* The reconstruction loop over every uploaded event; every scan, fit and
+ * classification runs with turn_stop on and sp's other settings (sp->precision must
+ * be 32). First partition: the Hough windows of all hits (hp), the n_candidates
+ * lowest-E seeds of each event (cutoff sp->lambda_mm2); each is fitted by
+ * Gauss-Newton (gn_iters, inlier set at sp's cutoff), rescanned over a (z0, pz0) grid
+ * of fine_count points within fine_half_width of its fitted values with the rest
+ * kept (scored at lambda_classify) and fitted again (inlier set at lambda_classify);
+ * the event keeps the candidate with the lowest E at lambda_classify and classifies
+ * the hits with (D - d)^2 < lambda_classify at it; they are removed. Then, on the side
+ * before the earliest and after the latest partition found, the neighbouring
+ * partition's seed is predicted from that partition's fitted seed
+ * (rkn_neighbour_seeds), a window of count[] seeds with half_width[] around it is
+ * scanned over the hits still unclassified (sp's cutoff), and its best seed is
+ * fitted at both cutoffs and classifies hits likewise (the earlier side first, then
+ * the later one, so no hit gets two partitions). A partition is kept when it
+ * classifies at least min_hits hits, else that side ends; an event ends when fewer
+ * than min_hits hits remain unclassified, both sides have ended or it has max_turns
+ * partitions. Outputs (host): hit_turn [total hits] = partition index in the order
+ * found, -1 unclassified; n_turns [n_events]; and, unless NULL, per event and
+ * partition ([n_events][max_turns]): turn_seed [..][5] the fitted seed, turn_center
+ * [..][5] the centre of the window its candidate came from (a Hough window for the
+ * first, the prediction otherwise), turn_pos the partition's place along the track
+ * relative to the first found (..., -1, 0, +1, ...), turn_nhits the hits it
+ * classified. The context's hits are replaced by the unclassified ones during the
+ * call and restored at the end (a planned batch or refinement must be set up again). */
+rkn_status rkn_find_turns(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp,
+                          const rkn_turn_params *tp, int32_t *hit_turn, int32_t *n_turns, double *turn_seed,
+                          double *turn_center, int32_t *turn_pos, int32_t *turn_nhits);
 
 /* ---- Differentiated refinement of seeds --------------------------------------------
  * The paper refines the best seeds by rescanning finer grids (section 2.2); this is

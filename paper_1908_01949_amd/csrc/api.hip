@@ -53,6 +53,7 @@ rkn_status check_scan_params(rkn_ctx* c, const rkn_scan_params* p) {
   if (p->block_steps != 0 && p->block_steps != 4 && p->block_steps != 6 && p->block_steps != 8)
     return arg_err(c, "block_steps must be 0, 4, 6 or 8");
   if (p->ptr_flags & ~RKN_PTR_DEVICE) return arg_err(c, "unknown ptr_flags bits");
+  if (p->turn_stop != 0 && p->turn_stop != 1) return arg_err(c, "turn_stop must be 0 or 1");
   return RKN_OK;
 }
 
@@ -302,6 +303,8 @@ rkn_status rkn_upload_hits(rkn_ctx* c, int32_t n_events, const int32_t* ev_off, 
   c->total_hits = H;
   c->max_hits_event = maxh;
   c->h_ev_off.assign(ev_off, ev_off + n_events + 1);
+  c->h_wire.assign(wire_id, wire_id + H);
+  c->h_drift.assign(drift, drift + H);
   return RKN_OK;
 }
 

@@ -146,7 +146,7 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
   if (!sp || sp->n_steps < 1 || !(sp->step_mm > 0) || !(sp->lambda_mm2 >= 0) || !(sp->R0 > 0) ||
       !std::isfinite(sp->charge) || sp->charge == 0 || (sp->precision != 32 && sp->precision != 64) ||
       (sp->block_steps != 0 && sp->block_steps != 4 && sp->block_steps != 6 && sp->block_steps != 8) ||
-      (sp->ptr_flags & ~RKN_PTR_DEVICE)) {
+      (sp->ptr_flags & ~RKN_PTR_DEVICE) || (sp->turn_stop != 0 && sp->turn_stop != 1)) {
     c->err = "batch: invalid scan parameters";
     return RKN_E_ARG;
   }

@@ -43,7 +43,8 @@ rkn_status cerr(rkn_ctx* c, hipError_t e, const char* where) {
 
 rkn_status check_params(rkn_ctx* c, const rkn_scan_params* p) {
   if (!p || p->n_steps < 1 || !(p->step_mm > 0) || !(p->lambda_mm2 >= 0) || !(p->R0 > 0) ||
-      !std::isfinite(p->charge) || p->charge == 0 || (p->ptr_flags & ~RKN_PTR_DEVICE)) {
+      !std::isfinite(p->charge) || p->charge == 0 || (p->ptr_flags & ~RKN_PTR_DEVICE) ||
+      (p->turn_stop != 0 && p->turn_stop != 1)) {
     c->err = "classify: invalid scan parameters";
     return RKN_E_ARG;
   }

@@ -129,6 +129,8 @@ struct rkn_ctx {
   int64_t total_hits = 0;
   int max_hits_event = 0;
   std::vector<int32_t> h_ev_off;
+  std::vector<int32_t> h_wire;    // host copies of the uploaded hits (upload order)
+  std::vector<float> h_drift;
   rkn::DevBuf ev_off, hits32, hits64, layer_off, ev_maxdrift;
   rkn::DevBuf hits_wire;             // int32 wire id per hit, upload order
   rkn::DevBuf hits_orig;             // int32 original index within its event, per layer-ordered hit

@@ -743,7 +743,8 @@ rkn_status rkn_refine_setup(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seed
                             const double* seeds5, int32_t ckpt_every) {
   if (!c) return RKN_E_ARG;
   if (!p || p->precision != 32 || p->n_steps < 1 || !(p->step_mm > 0) || !(p->lambda_mm2 >= 0) || !(p->R0 > 0) ||
-      !std::isfinite(p->charge) || p->charge == 0 || (p->ptr_flags & ~RKN_PTR_DEVICE)) {
+      !std::isfinite(p->charge) || p->charge == 0 || (p->ptr_flags & ~RKN_PTR_DEVICE) ||
+      (p->turn_stop != 0 && p->turn_stop != 1)) {
     c->err = "refine: parameters must be valid with precision 32";
     return RKN_E_ARG;
   }

@@ -63,6 +63,7 @@ struct ScanArgs {
   int64_t slab_stride;        // elements per workgroup slab
   double R0, charge, h, lambda;
   int n_steps;
+  int turn_stop;              // 1: a lane's track ends with the first step inside r < R0
   double* score;
   int32_t* nin;
   ArgminPart* parts;
@@ -475,7 +476,17 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     const int nblocks = (a.n_steps + B - 1) / B;
     const R Kcull = (R)(0.5 * B * a.h + sqrt(lam) + (double)kCullMargin);
     const R sqrt_lam = (R)sqrt(lam);
+    // end of the turn partition: once a step ends inside r < R0 the lane's state is
+    // frozen, so its later chords have zero length at that end point and cannot
+    // lower any distance; a block that starts frozen is not culled at all, and a
+    // wave whose lanes are all frozen leaves the loop (unless a tape needs states)
+    const bool stop_on = a.turn_stop != 0;
+    const R r0sq = (R)(a.R0 * a.R0);
+    const bool may_exit = stop_on && !(MODE == 1 && a.tape);
+    bool live = true;
     for (int blk = 0; blk < nblocks; ++blk) {
+      if (may_exit && __ballot(live) == 0) break;
+      const bool live0 = live;
       const int nb = min(B, a.n_steps - blk * B);
       const int jc = nb / 2;
       if constexpr (MODE == 1) {
@@ -496,11 +507,12 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       R cx = st.x, cy = st.y, cz = st.z;
 #pragma unroll
       for (int j = 1; j <= B; ++j) {
-        if (j <= nb) rkn_step<R, FIELD>(st, a.field, nodes, h);
+        if (j <= nb && live) rkn_step<R, FIELD>(st, a.field, nodes, h);
         pts[(j * 3 + 0) * 64 + lane] = st.x;
         pts[(j * 3 + 1) * 64 + lane] = st.y;
         pts[(j * 3 + 2) * 64 + lane] = st.z;
         const R r2 = st.x * st.x + st.y * st.y;
+        live = live && !(stop_on && r2 < r0sq);
         r2min = r2 < r2min ? r2 : r2min;
         r2max = r2 > r2max ? r2 : r2max;
         if (j == jc) {
@@ -519,7 +531,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       // hits that can reach the azimuth sector of the block's middle point; each lane
       // walks its own runs, hit records gathered from LDS
       const int L0 = s_ltab[b_lo] & 0xff, L1p = s_ltab[b_hi] >> 8;
-      const int n_lay = valid ? max(L1p - L0, 0) : 0;
+      const int n_lay = (valid && live0) ? max(L1p - L0, 0) : 0;
       const float phic = sector_atan2((float)cy, (float)cx);
       int n_items = 0;
       for (int dl = 0; __ballot(dl < n_lay) != 0; ++dl) {
@@ -583,6 +595,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           if (in) ph += r * r;
         }
         for (int i = nh; i < a.max_hits; ++i) {
+          if (a.define_mask) mrow[i] = 0;   // the whole row is defined, unused columns 0
           rrow[i] = NAN;
           arow[i] = -1;
         }
@@ -834,6 +847,7 @@ hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_til
   a.h = p->step_mm;
   a.lambda = p->lambda_mm2;
   a.n_steps = p->n_steps;
+  a.turn_stop = p->turn_stop;
   a.hits_orig = c->hits_orig.as<int32_t>();
   a.base_of = d_base_of;
   a.mask = d_mask;
@@ -872,6 +886,7 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   a.h = p->step_mm;
   a.lambda = p->lambda_mm2;
   a.n_steps = p->n_steps;
+  a.turn_stop = p->turn_stop;
   a.score = d_score;
   a.nin = d_nin;
   a.parts = parts.as<ArgminPart>();
@@ -921,7 +936,7 @@ hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_til
 // ---------------------------------------------------------------------------------
 template <typename R, int FIELD>
 __global__ void __launch_bounds__(256)
-trace_kernel(FieldDev f, double R0, double charge, double hstep, int64_t n_seeds,
+trace_kernel(FieldDev f, double R0, double charge, double hstep, int turn_stop, int64_t n_seeds,
              const double* __restrict__ seeds, int n_sel, const int32_t* __restrict__ steps,
              double* __restrict__ out) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -944,12 +959,14 @@ trace_kernel(FieldDev f, double R0, double charge, double hstep, int64_t n_seeds
   st.cx = st.cy = st.cz = (R)0;
       st.ctx = st.cty = st.ctz = (R)0;
   const R h = (R)hstep;
+  const R r0sq = (R)(R0 * R0);
   int n = 0;
+  bool live = true;   // with turn_stop, states after the end of the turn partition stay
   for (int k = 0; k < n_sel; ++k) {
     const int target = steps[k];
-    while (n < target) {
+    for (; n < target && live; ++n) {
       rkn_step<R, FIELD>(st, f, f.nodes, h);
-      ++n;
+      live = !(turn_stop && st.x * st.x + st.y * st.y < r0sq);
     }
     o[6 * k + 0] = (double)st.x;
     o[6 * k + 1] = (double)st.y;
@@ -968,17 +985,17 @@ hipError_t launch_trace(rkn_ctx* c, const rkn_scan_params* p, int64_t n_seeds, c
   if (p->precision == 64) {
     if (c->field_kind == 0)
       hipLaunchKernelGGL((trace_kernel<double, 0>), grid, block, 0, c->stream, f, p->R0, p->charge,
-                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+                         p->step_mm, p->turn_stop, n_seeds, d_seeds, n_sel, d_steps, d_states);
     else
       hipLaunchKernelGGL((trace_kernel<double, 1>), grid, block, 0, c->stream, f, p->R0, p->charge,
-                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+                         p->step_mm, p->turn_stop, n_seeds, d_seeds, n_sel, d_steps, d_states);
   } else {
     if (c->field_kind == 0)
       hipLaunchKernelGGL((trace_kernel<float, 0>), grid, block, 0, c->stream, f, p->R0, p->charge,
-                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+                         p->step_mm, p->turn_stop, n_seeds, d_seeds, n_sel, d_steps, d_states);
     else
       hipLaunchKernelGGL((trace_kernel<float, 1>), grid, block, 0, c->stream, f, p->R0, p->charge,
-                         p->step_mm, n_seeds, d_seeds, n_sel, d_steps, d_states);
+                         p->step_mm, p->turn_stop, n_seeds, d_seeds, n_sel, d_steps, d_states);
   }
   return hipGetLastError();
 }

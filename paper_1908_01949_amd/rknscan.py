@@ -56,7 +56,18 @@ class rkn_hough_params(C.Structure):
 class rkn_scan_params(C.Structure):
     _fields_ = [("R0", C.c_double), ("charge", C.c_double), ("step_mm", C.c_double),
                 ("lambda_mm2", C.c_double), ("n_steps", C.c_int32), ("precision", C.c_int32),
-                ("ptr_flags", C.c_int32), ("block_steps", C.c_int32)]
+                ("ptr_flags", C.c_int32), ("block_steps", C.c_int32), ("turn_stop", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class rkn_turn_params(C.Structure):
+    _fields_ = [("half_width", C.c_double * 5), ("count", C.c_int32 * 5), ("gn_iters", C.c_int32),
+                ("gn_scale", C.c_double * 5), ("lambda_classify_mm2", C.c_double),
+                ("fine_half_width", C.c_double * 2), ("fine_count", C.c_int32 * 2), ("n_candidates", C.c_int32),
+                ("min_hits", C.c_int32), ("max_turns", C.c_int32), ("max_extrap_steps", C.c_int32)]
+
+
+RKN_TURNS_MAX = 16
 
 
 # Exported symbols and their ctypes signatures (the C header declares the same set).
@@ -92,6 +103,8 @@ _SIGS = {
     "rkn_residuals_fwd": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_adjoint_bwd": (C.c_int32, [_P, _P, _P, _P, _P]),
     "rkn_gn_refine": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "rkn_neighbour_seeds": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, C.c_int32, _P, _P]),
+    "rkn_find_turns": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -198,8 +211,9 @@ def rkn_upload_hits(ctx, ev_off, wire_id, drift) -> None:
 
 
 def make_scan_params(R0=500.0, charge=-1.0, step_mm=1.0, lambda_mm2=64.0, n_steps=2000, precision=32,
-                     ptr_flags=0, block_steps=0) -> rkn_scan_params:
-    return rkn_scan_params(R0, charge, step_mm, lambda_mm2, n_steps, precision, ptr_flags, block_steps)
+                     ptr_flags=0, block_steps=0, turn_stop=0) -> rkn_scan_params:
+    return rkn_scan_params(R0, charge, step_mm, lambda_mm2, n_steps, precision, ptr_flags, block_steps,
+                           int(turn_stop), 0)
 
 
 def make_hough_params(**kw) -> rkn_hough_params:
@@ -356,6 +370,50 @@ def rkn_classify_hits(ctx, p: rkn_scan_params, seed_event, seeds5, n_hits_max, m
     _check(ctx, load_library().rkn_classify_hits(ctx, C.byref(p), se.size, _ptr(se), _ptr(s5), _ptr(mask),
                                                  _ptr(n_in)))
     return mask, n_in
+
+
+def make_turn_params(half_width=(0.01, 20.0, 2.0, 2.0, 2.0), count=(5, 9, 5, 5, 9), gn_iters=10,
+                     gn_scale=(1.0, 100.0, 100.0, 100.0, 100.0), lambda_classify_mm2=4.0,
+                     fine_half_width=(300.0, 24.0), fine_count=(61, 49), n_candidates=4, min_hits=10,
+                     max_turns=8, max_extrap_steps=6000) -> rkn_turn_params:
+    tp = rkn_turn_params()
+    for i in range(5):
+        tp.half_width[i] = half_width[i]
+        tp.count[i] = count[i]
+        tp.gn_scale[i] = gn_scale[i]
+    for i in range(2):
+        tp.fine_half_width[i] = fine_half_width[i]
+        tp.fine_count[i] = fine_count[i]
+    tp.n_candidates = n_candidates
+    tp.gn_iters = gn_iters
+    tp.lambda_classify_mm2 = lambda_classify_mm2
+    tp.min_hits = min_hits
+    tp.max_turns = max_turns
+    tp.max_extrap_steps = max_extrap_steps
+    return tp
+
+
+def rkn_neighbour_seeds(ctx, p: rkn_scan_params, seeds5, direction, max_steps=6000, out5=None, found=None):
+    """Seeds of the neighbouring turn partitions ([n][5]) and the found flags."""
+    s5 = np.ascontiguousarray(np.asarray(seeds5, np.float64).reshape(-1, 5))
+    n = s5.shape[0]
+    if out5 is None:
+        out5 = np.zeros((n, 5)); found = np.zeros(n, np.int32)
+    _check(ctx, load_library().rkn_neighbour_seeds(ctx, C.byref(p), n, _ptr(s5), int(direction), int(max_steps),
+                                                   _ptr(out5), _ptr(found)))
+    return out5, found
+
+
+def rkn_find_turns(ctx, hp: rkn_hough_params, sp: rkn_scan_params, tp: rkn_turn_params, n_hits_total, n_events):
+    """The turn-partition loop; returns a dict of its outputs (host arrays)."""
+    T = int(tp.max_turns)
+    out = dict(hit_turn=np.zeros(n_hits_total, np.int32), n_turns=np.zeros(n_events, np.int32),
+               turn_seed=np.zeros((n_events, T, 5)), turn_center=np.zeros((n_events, T, 5)),
+               turn_pos=np.zeros((n_events, T), np.int32), turn_nhits=np.zeros((n_events, T), np.int32))
+    _check(ctx, load_library().rkn_find_turns(ctx, C.byref(hp), C.byref(sp), C.byref(tp), _ptr(out["hit_turn"]),
+                                              _ptr(out["n_turns"]), _ptr(out["turn_seed"]), _ptr(out["turn_center"]),
+                                              _ptr(out["turn_pos"]), _ptr(out["turn_nhits"])))
+    return out
 
 
 def rkn_bidirectional_common(ctx, p: rkn_scan_params, pair_event, seeds_entry5, seeds_exit5, n_hits_max,

@@ -37,8 +37,34 @@ def test_struct_layouts_match_header():
     import ctypes
     from paper_1908_01949_amd import rknscan, synth
     assert ctypes.sizeof(rknscan.rkn_window) == 112 == synth.WINDOW_DTYPE.itemsize
-    assert ctypes.sizeof(rknscan.rkn_scan_params) == 48
+    assert ctypes.sizeof(rknscan.rkn_scan_params) == 56
     assert ctypes.sizeof(rknscan.rkn_hough_params) == 4 * 2 + 8 * 3 + 4 * 2 + 8 * 3 + 8 * 5 + 8 * 2 + 4 * 5 * 2 + 4 * 2 + 8
+    assert ctypes.sizeof(rknscan.rkn_turn_params) == 152
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """Sizes and field offsets of the binding's structs equal what a C compiler makes
+    of the header."""
+    import ctypes
+    import subprocess
+    from paper_1908_01949_amd import rknscan
+    structs = {"rkn_window": rknscan.rkn_window, "rkn_scan_params": rknscan.rkn_scan_params,
+               "rkn_hough_params": rknscan.rkn_hough_params, "rkn_turn_params": rknscan.rkn_turn_params}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rknscan.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
 
 
 def test_no_oracle_import_in_product():

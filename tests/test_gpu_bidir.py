@@ -103,3 +103,26 @@ def test_exit_side_windows_and_common_hits(rk, geo, sfield, orc_s):
         # the paper's quality cut keeps these clean single-track events
         assert n_common[e] >= 20
     c.close()
+
+
+def test_mask_rows_fully_defined(rk, geo, sfield):
+    """Columns past an event's hit count are 0 even where the buffers held ones from
+    an earlier classification of larger events, so the counts only see real hits."""
+    big = [synth.event_fixed_total(geo, sfield, s, n_total=150, noise_frac=0.3) for s in (4, 5)]
+    small = [synth.event_fixed_total(geo, sfield, s, n_total=n, noise_frac=0.1) for s, n in ((6, 60), (7, 45))]
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield)
+    p = rk.make_scan_params(n_steps=N_STEPS, precision=32, lambda_mm2=1e6)   # every reached hit is in
+    for evs in (big, small):
+        off, wid, dr = synth.pack_events(evs)
+        c.upload_hits(off, wid, dr)
+        H = int(np.diff(off).max())
+        ev = np.array([0, 1, 0, 1], np.int32)
+        s5 = np.array([evs[e].truth_seeds[0] for e in ev])
+        mask, n_in = rk.rkn_classify_hits(c.ctx, p, ev, s5, H)
+        for i, e in enumerate(ev):
+            nh = evs[e].wire_id.size
+            assert not mask[i, nh:].any() and n_in[i] == int(mask[i].sum()) > 0
+        _, _, n_common = rk.rkn_bidirectional_common(c.ctx, p, ev, s5, s5, H)
+        assert np.all(n_common <= np.diff(off)[ev])
+    c.close()
