@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 from paper_1908_01949_amd import rknscan as rk  # noqa: E402  (loads the HIP runtime first)
-from paper_1908_01949_amd import flops, synth, workloads  # noqa: E402
+from paper_1908_01949_amd import flops, quality, synth, workloads  # noqa: E402
 
 METRIC = "RKN seed-steps/s & events/s, %FP32 vector peak; plain scan vs adjoint-refined"
 
@@ -278,6 +278,42 @@ def bidirectional_leg(ctx, field, sp, n_events, t_entrance, n_hits_max, n_c_min=
                 events_kept=kept, n_c_min=n_c_min, n_c_mean=float(n_common.mean()) if ev.size else 0.0)
 
 
+def turns_leg(geo, field, n_events):
+    """Section 2.3's reconstruction loop over multi-turn events (2-3 passes, 30 % noise)
+    in the same field: time per call (inputs resident, host outputs) and the track
+    finding quality of Eqs. 2-3 against the synthetic truth, averaged over the true
+    turn partitions."""
+    wl = workloads.TURNS
+    t0 = time.time()
+    evs = synth.events_multi_turn(geo, field, n_events, seed=1, n_steps=wl["n_steps"])
+    off, wid, dr = synth.pack_events(evs)
+    log(f"turn partitions: {n_events} multi-turn events, {wid.size} hits in {time.time() - t0:.1f} s")
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(field); c.upload_hits(off, wid, dr)
+    hp = rk.make_hough_params(b_ref=field.b_ref, **wl["hough"])
+    sp = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    tp = rk.make_turn_params()
+    rk.rkn_find_turns(c.ctx, hp, sp, tp, wid.size, n_events)       # warm-up (code objects, buffers)
+    r, dt = _sync_time(lambda: rk.rkn_find_turns(c.ctx, hp, sp, tp, wid.size, n_events))
+    c.close()
+    eps, pur, last_eps, last_pur = [], [], [], []
+    for e, x in enumerate(evs):
+        q = quality.turn_quality(x.turn_of, r["hit_turn"][off[e]:off[e + 1]])
+        eps += [v["eps"] for v in q]
+        pur += [v["pi"] for v in q if np.isfinite(v["pi"])]
+        last_eps.append(q[-1]["eps"])
+        if np.isfinite(q[-1]["pi"]):
+            last_pur.append(q[-1]["pi"])
+    out = dict(events=n_events, ms=round(dt * 1e3, 1), events_per_s=n_events / dt,
+               partitions_per_event=float(r["n_turns"].mean()),
+               true_partitions_per_event=float(np.mean([x.turn_of.max() + 1 for x in evs])),
+               mean_eps=float(np.mean(eps)), mean_pi=float(np.mean(pur)),
+               last_turn_eps=float(np.mean(last_eps)), last_turn_pi=float(np.mean(last_pur)),
+               unclassified_frac=float(np.mean(r["hit_turn"] < 0)))
+    log(f"turn partitions: {out}")
+    return out
+
+
 def other_workloads(geo, reps=3):
     """The single-event workloads, timed on the GPU (device outputs, inputs resident):
     a 6^5 FP64 scan of a single-turn event, a 16^5 FP32 scan of a multi-turn event
@@ -340,6 +376,8 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement comparison")
     ap.add_argument("--no-other", action="store_true", help="skip the single-event workloads")
     ap.add_argument("--no-bidir", action="store_true", help="skip the two-direction scan")
+    ap.add_argument("--turn-events", type=int, default=workloads.TURNS["n_events"],
+                    help="multi-turn events of the turn-partition loop (0 = skip)")
     ap.add_argument("--block-steps", type=int, default=0, help="RKN steps per cull block (0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
@@ -435,6 +473,8 @@ def main():
     if not args.no_bidir:
         out["bidirectional"] = bidirectional_leg(ctx, field, sp, ne, dt / args.steps, int(np.diff(off).max()))
     ctx.close()
+    if args.turn_events > 0:
+        out["turn_partitions"] = turns_leg(geo, field, args.turn_events)
     if not args.no_other:
         out["other_workloads"] = other_workloads(geo)
     print(json.dumps(out))

@@ -667,6 +667,37 @@ def events_batch(geo: Geometry, field: Field, n_events: int = 512, seed: int = 0
     return events
 
 
+def events_multi_turn(geo: Geometry, field: Field, n_events: int, seed: int = 0, n_steps: int = 6000,
+                      noise_frac: float = 0.30, sigma: float = 0.2, p: float = P_SIGNAL,
+                      true_range=(100, 140), min_passes: int = 2, truth_step: float = 1.0) -> list[Event]:
+    """Many multi-turn events as event_multi_turn makes one (one 2-3 pass e- with
+    |pz| ~ U[5,20] MeV/c, 100-140 true hits, 30 % noise, per-hit true pass), with the
+    candidate tracks traced together."""
+    rng = np.random.default_rng([BASE_SEED, 5, seed])
+    tf = TruthField(field)
+    events: list[Event] = []
+    while len(events) < n_events:
+        k = 8 * (n_events - len(events)) + 8
+        pz = rng.uniform(5.0, 20.0, k) * rng.choice([-1.0, 1.0], k)
+        pt = np.sqrt(p * p - pz * pz)
+        ph = 2 * np.pi * rng.random(k)
+        pv = np.stack([pt * np.cos(ph), pt * np.sin(ph), pz], -1)
+        v = _draw_vertex(rng, k)
+        for tr in trace_truth(tf, v, pv, ELECTRON_Q, n_steps - 20.0, h=truth_step):
+            if tr is None or len(events) >= n_events:
+                continue
+            r = np.hypot(tr.x[:, 0], tr.x[:, 1])
+            passes = int(np.sum((r[:-1] < geo.layer_rmin[0]) & (r[1:] >= geo.layer_rmin[0])))
+            if passes < min_passes:
+                continue
+            w, d, s = true_wire_distances(geo, tr, n_steps - 20.0)
+            if true_range[0] <= w.size <= true_range[1]:
+                n_noise = int(round(noise_frac * w.size))
+                events.append(_finish_event(rng, geo, w, d, np.zeros(w.size), [tr.seed], [p], n_noise, sigma,
+                                            turn_of=turn_index(tr, s)))
+    return events
+
+
 def pack_events(events: list[Event]):
     """CSR layout for the hit upload: (ev_off[E+1] int32, wire_id[H] int32, drift[H] float32)."""
     off = np.zeros(len(events) + 1, dtype=np.int32)
