@@ -328,7 +328,7 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R, int FIELD, int B, int WAVES, int MODE>
+template <typename R, int FIELD, int B, int WAVES, int MODE, bool STOP>
 __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   constexpr int TILE = 64 * WAVES;
   // MODE 0: the scan (score E). MODE 1: the refinement forward pass (FP32 only):
@@ -476,16 +476,17 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     const int nblocks = (a.n_steps + B - 1) / B;
     const R Kcull = (R)(0.5 * B * a.h + sqrt(lam) + (double)kCullMargin);
     const R sqrt_lam = (R)sqrt(lam);
-    // end of the turn partition: once a step ends inside r < R0 the lane's state is
-    // frozen, so its later chords have zero length at that end point and cannot
-    // lower any distance; a block that starts frozen is not culled at all, and a
-    // wave whose lanes are all frozen leaves the loop (unless a tape needs states)
-    const bool stop_on = a.turn_stop != 0;
+    // STOP (the end of the turn partition): once a step ends inside r < R0 the
+    // lane's state is frozen, so its later chords have zero length at that end point
+    // and cannot lower any distance; a block that starts frozen is not culled at all,
+    // and a wave whose lanes are all frozen leaves the loop (unless a tape needs states)
     const R r0sq = (R)(a.R0 * a.R0);
-    const bool may_exit = stop_on && !(MODE == 1 && a.tape);
+    const bool may_exit = STOP && !(MODE == 1 && a.tape);
     bool live = true;
     for (int blk = 0; blk < nblocks; ++blk) {
-      if (may_exit && __ballot(live) == 0) break;
+      if constexpr (STOP) {
+        if (may_exit && __ballot(live) == 0) break;
+      }
       const bool live0 = live;
       const int nb = min(B, a.n_steps - blk * B);
       const int jc = nb / 2;
@@ -507,12 +508,12 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       R cx = st.x, cy = st.y, cz = st.z;
 #pragma unroll
       for (int j = 1; j <= B; ++j) {
-        if (j <= nb && live) rkn_step<R, FIELD>(st, a.field, nodes, h);
+        if (j <= nb && (!STOP || live)) rkn_step<R, FIELD>(st, a.field, nodes, h);
         pts[(j * 3 + 0) * 64 + lane] = st.x;
         pts[(j * 3 + 1) * 64 + lane] = st.y;
         pts[(j * 3 + 2) * 64 + lane] = st.z;
         const R r2 = st.x * st.x + st.y * st.y;
-        live = live && !(stop_on && r2 < r0sq);
+        if constexpr (STOP) live = live && !(r2 < r0sq);
         r2min = r2 < r2min ? r2 : r2min;
         r2max = r2 > r2max ? r2 : r2max;
         if (j == jc) {
@@ -531,7 +532,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       // hits that can reach the azimuth sector of the block's middle point; each lane
       // walks its own runs, hit records gathered from LDS
       const int L0 = s_ltab[b_lo] & 0xff, L1p = s_ltab[b_hi] >> 8;
-      const int n_lay = (valid && live0) ? max(L1p - L0, 0) : 0;
+      const int n_lay = (valid && (!STOP || live0)) ? max(L1p - L0, 0) : 0;
       const float phic = sector_atan2((float)cy, (float)cx);
       int n_items = 0;
       for (int dl = 0; __ballot(dl < n_lay) != 0; ++dl) {
@@ -698,7 +699,7 @@ static size_t sect_table_bytes(const rkn_ctx* c) {
   return ((size_t)std::max(c->n_layers, 1) * kSectors * 4 + 255) & ~(size_t)255;
 }
 
-// LDS bytes of one workgroup of scan_kernel<R, FIELD, B, WAVES>.
+// LDS bytes of one workgroup of scan_kernel<R, FIELD, B, WAVES, ...>.
 static size_t scan_lds_bytes(const rkn_ctx* c, size_t rsize, int field, int B, int waves) {
   const size_t hits = ((size_t)c->max_hits_event * (rsize == 4 ? sizeof(HitRec<float>) : sizeof(HitRec<double>)) +
                        255) & ~(size_t)255;
@@ -736,7 +737,9 @@ template <typename R, int FIELD, int B, int WAVES>
 static bool shape_fits(const rkn_ctx* c) {
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return false;
-  return resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0>, 64 * WAVES, smem) >= 1;
+  // both variants (with and without the turn-partition stop) must fit the shape
+  return resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0, false>, 64 * WAVES, smem) >= 1 &&
+         resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0, true>, 64 * WAVES, smem) >= 1;
 }
 
 // Waves per workgroup. The FP32 field-map path stages the map in LDS once per
@@ -761,7 +764,7 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   a.sect_bytes = (int)sect_table_bytes(c);
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
-  auto kern = scan_kernel<R, FIELD, B, WAVES, MODE>;
+  auto kern = a.turn_stop ? scan_kernel<R, FIELD, B, WAVES, MODE, true> : scan_kernel<R, FIELD, B, WAVES, MODE, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int per_cu = resident_per_cu(c, (const void*)kern, TILE, smem);
