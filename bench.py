@@ -359,6 +359,16 @@ def other_workloads(geo, reps=3):
         dt = (time.perf_counter() - t) / reps
         out[name] = dict(seeds=n, steps=wl["n_steps"], ms_scan=round(dt * 1e3, 3),
                          seed_steps_per_s=n * wl["n_steps"] / dt, hough_ms=round(t_hough * 1e3, 3) or None)
+        if wl["precision"] == 32:
+            # the paper's record-then-DCA form of the same scan (section 4.2), for comparison
+            rk.rkn_scan_windows_two_kernel(c.ctx, p, w, score, None, bi, bs)
+            rk.rkn_synchronize(c.ctx)
+            t = time.perf_counter()
+            rk.rkn_scan_windows_two_kernel(c.ctx, p, w, score, None, bi, bs)
+            rk.rkn_synchronize(c.ctx)
+            t2 = time.perf_counter() - t
+            out[name]["ms_two_kernel"] = round(t2 * 1e3, 3)
+            out[name]["fused_speedup_over_two_kernel"] = round(t2 / dt, 2)
         log(f"{name}: {out[name]}")
         c.close()
     return out

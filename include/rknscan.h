@@ -197,6 +197,19 @@ rkn_status rkn_scan_windows_topk(rkn_ctx *ctx, const rkn_scan_params *p, int32_t
                                  const rkn_window *w, int32_t k, int64_t *index, double *score,
                                  double *seeds5);
 
+/* The same outputs as rkn_scan_windows, computed by the paper's two-kernel form of
+ * the scan (section 4.2), kept as an experiment beside the fused kernel: a record
+ * kernel stores every seed's position after each step in HBM (12 bytes per seed and
+ * step, in chunks of at most 4 GiB), then a DCA kernel gives each hit of the seed's
+ * event its own lane (one wave per seed) and finds its distance from the recorded
+ * chords (blocks of 8 chords pruned by the fused kernel's reach test). Same FP32
+ * state, step and chord/wire distance as the fused kernel; p->precision must be 32;
+ * block_steps is ignored; turn_stop is honoured. Outputs follow p->ptr_flags; any
+ * may be NULL. */
+rkn_status rkn_scan_windows_two_kernel(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_windows,
+                                       const rkn_window *w, double *score, int32_t *n_in, int64_t *best_index,
+                                       double *best_score);
+
 /* Same score for an explicit seed list (SoA, host arrays, FP64). best_index is the
  * position in the list. */
 rkn_status rkn_scan_seeds(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds,

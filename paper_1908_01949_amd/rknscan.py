@@ -105,6 +105,7 @@ _SIGS = {
     "rkn_gn_refine": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "rkn_neighbour_seeds": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, C.c_int32, _P, _P]),
     "rkn_find_turns": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "rkn_scan_windows_two_kernel": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -268,6 +269,15 @@ def rkn_scan_windows(ctx, p: rkn_scan_params, windows, score=None, n_in=None, be
     w = windows_to_c(windows)
     _check(ctx, load_library().rkn_scan_windows(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
                                                 _ptr(best_index), _ptr(best_score)))
+    return score, n_in, best_index, best_score
+
+
+def rkn_scan_windows_two_kernel(ctx, p: rkn_scan_params, windows, score=None, n_in=None, best_index=None,
+                                best_score=None):
+    """rkn_scan_windows computed by the record-then-DCA kernels (same outputs)."""
+    w = windows_to_c(windows)
+    _check(ctx, load_library().rkn_scan_windows_two_kernel(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
+                                                           _ptr(best_index), _ptr(best_score)))
     return score, n_in, best_index, best_score
 
 
