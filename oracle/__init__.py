@@ -46,6 +46,10 @@ class OrcParams(C.Structure):
                 ("lambda_mm2", C.c_double), ("n_steps", C.c_int32), ("turn_stop", C.c_int32)]
 
 
+class OrcAdaptive(C.Structure):
+    _fields_ = [("tol_mm", C.c_double), ("h_min_mm", C.c_double), ("h_max_mm", C.c_double)]
+
+
 class OrcWindow(C.Structure):
     _fields_ = [("event", C.c_int32), ("candidate", C.c_int32), ("center", C.c_double * 5),
                 ("half_width", C.c_double * 5), ("count", C.c_int32 * 5), ("pad", C.c_int32)]
@@ -94,6 +98,10 @@ def lib():
         _lib.orc_hough_window.argtypes = [P, P, C.c_int64, P]
         _lib.orc_hough_seed_windows.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P]
         _lib.orc_neighbour_seed.argtypes = [P, P, P, C.c_int32, C.c_int32, P]
+        _lib.orc_rkn_trial.argtypes = [P, C.c_double, C.c_double, P, P, P, P, P]
+        _lib.orc_adaptive_trace.argtypes = [P, P, P, P, C.c_int32, P, P, P]
+        _lib.orc_score_adaptive.restype = C.c_double
+        _lib.orc_score_adaptive.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, P]
     return _lib
 
 
@@ -155,6 +163,27 @@ class Oracle:
         ok = lib().orc_neighbour_seed(C.byref(self.field), C.byref(prm), _ptr(s), int(direction), int(max_steps),
                                       _ptr(out))
         return out if ok else None
+
+    # ---- adaptive step size ---------------------------------------------------------
+    def rkn_trial(self, lam, h, x, T):
+        x = np.ascontiguousarray(x, np.float64); T = np.ascontiguousarray(T, np.float64)
+        xn = np.zeros(3); Tn = np.zeros(3); err = C.c_double()
+        lib().orc_rkn_trial(C.byref(self.field), lam, h, _ptr(x), _ptr(T), _ptr(xn), _ptr(Tn), C.byref(err))
+        return xn, Tn, err.value
+
+    def adaptive_trace(self, prm, ap, seed, max_pts=100000):
+        s = np.ascontiguousarray(seed, np.float64)
+        pts = np.zeros((max_pts, 3)); arc = np.zeros(max_pts); rej = C.c_int32()
+        n = lib().orc_adaptive_trace(C.byref(self.field), C.byref(prm), C.byref(ap), _ptr(s), max_pts, _ptr(pts),
+                                     _ptr(arc), C.byref(rej))
+        return pts[:n], arc[:n], rej.value
+
+    def score_adaptive(self, prm, ap, seed, wire_id, drift):
+        s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
+        d = np.ascontiguousarray(drift, np.float32); n_in = C.c_int32(); ns = C.c_int32()
+        E = lib().orc_score_adaptive(C.byref(self.geo), C.byref(self.field), C.byref(prm), C.byref(ap), _ptr(s),
+                                     w.size, _ptr(w), _ptr(d), C.byref(n_in), C.byref(ns))
+        return E, n_in.value, ns.value
 
     # ---- distances and score -----------------------------------------------------
     @staticmethod

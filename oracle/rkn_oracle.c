@@ -1098,3 +1098,106 @@ int orc_neighbour_seed(const orc_field *f, const orc_params *p, const double see
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Adaptive step size. Reading of the error-controlled RKN that section 2.2 cites:
+ * the stages of one Nystrom step also give a local error estimate,
+ * err = h^2 |k1 - k2 - k3 + k4| (the four stage accelerations agree to O(h^2) for a
+ * smooth force, so err is O(h^4)). A trial step is accepted when err <= tol, or when
+ * h is already the smallest step; the next step is h times 0.9 (tol/err)^(1/4),
+ * clamped to [1/4, 4] and to [h_min, h_max] (a rejected trial retries with the same
+ * rule, never growing), and the last step is cut to end the path exactly at length
+ * L = n_steps * step_mm. The first trial uses h_max.                            */
+void orc_rkn_trial(const orc_field *f, double Lam, double h, const double x[3], const double T[3],
+                   double xn[3], double Tn[3], double *err) {
+  double k1[3], k2[3], k3[3], k4[3], xm[3], xe[3], Tt[3], e2 = 0.0;
+  int c;
+  accel(f, Lam, x, T, k1);
+  for (c = 0; c < 3; ++c) xm[c] = x[c] + 0.5 * h * T[c] + 0.125 * h * h * k1[c];
+  for (c = 0; c < 3; ++c) Tt[c] = T[c] + 0.5 * h * k1[c];
+  accel(f, Lam, xm, Tt, k2);
+  for (c = 0; c < 3; ++c) Tt[c] = T[c] + 0.5 * h * k2[c];
+  accel(f, Lam, xm, Tt, k3);
+  for (c = 0; c < 3; ++c) xe[c] = x[c] + h * T[c] + 0.5 * h * h * k3[c];
+  for (c = 0; c < 3; ++c) Tt[c] = T[c] + h * k3[c];
+  accel(f, Lam, xe, Tt, k4);
+  for (c = 0; c < 3; ++c) {
+    double d = k1[c] - k2[c] - k3[c] + k4[c];
+    xn[c] = x[c] + h * T[c] + (h * h / 6.0) * (k1[c] + k2[c] + k3[c]);
+    Tn[c] = T[c] + (h / 6.0) * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+    e2 += d * d;
+  }
+  *err = h * h * sqrt(e2);
+}
+
+static double next_step(const orc_adaptive *a, double h, double err, int accepted) {
+  double g = err > 0.0 ? 0.9 * pow(a->tol_mm / err, 0.25) : 4.0;
+  if (g > 4.0) g = 4.0;
+  if (g < 0.25) g = 0.25;
+  if (!accepted && g > 1.0) g = 1.0;
+  h *= g;
+  if (h > a->h_max_mm) h = a->h_max_mm;
+  if (h < a->h_min_mm) h = a->h_min_mm;
+  return h;
+}
+
+int orc_adaptive_trace(const orc_field *f, const orc_params *p, const orc_adaptive *a, const double seed[5],
+                       int32_t max_pts, double *pts, double *s, int32_t *n_rejected) {
+  double x[3], T[3], Lam, L = p->n_steps * p->step_mm, arc = 0.0, h = a->h_max_mm;
+  int32_t n = 0, rej = 0, c;
+  if (n_rejected) *n_rejected = 0;
+  if (max_pts < 1 || !orc_seed_state(p, seed, x, T, &Lam)) return 0;
+  for (c = 0; c < 3; ++c) pts[c] = x[c];
+  s[0] = 0.0;
+  n = 1;
+  while (arc < L && n < max_pts) {
+    double xn[3], Tn[3], err, hs = h < L - arc ? h : L - arc;
+    orc_rkn_trial(f, Lam, hs, x, T, xn, Tn, &err);
+    if (err <= a->tol_mm || hs <= a->h_min_mm) {
+      for (c = 0; c < 3; ++c) { x[c] = xn[c]; T[c] = Tn[c]; pts[3 * n + c] = x[c]; }
+      arc += hs;
+      s[n] = arc;
+      ++n;
+      if (hs == h) h = next_step(a, h, err, 1);   /* a cut last step does not set h */
+      if (turn_ended(p, x)) break;
+    } else {
+      ++rej;
+      h = next_step(a, hs, err, 0);
+    }
+  }
+  if (n_rejected) *n_rejected = rej;
+  return n;
+}
+
+double orc_score_adaptive(const orc_geometry *g, const orc_field *f, const orc_params *p, const orc_adaptive *a,
+                          const double seed[5], int32_t n_hits, const int32_t *wire_id, const float *drift,
+                          int32_t *n_in, int32_t *n_steps_taken) {
+  int32_t cap = 4 * (int32_t)ceil(p->n_steps * p->step_mm / a->h_min_mm) + 8, n, i, j, cnt = 0;
+  double *pts = (double *)malloc(sizeof(double) * 3 * cap), *s = (double *)malloc(sizeof(double) * cap);
+  double E = 0.0;
+  n = orc_adaptive_trace(f, p, a, seed, cap, pts, s, NULL);
+  if (n_steps_taken) *n_steps_taken = n > 0 ? n - 1 : 0;
+  if (n == 0) {
+    free(pts); free(s);
+    if (n_in) *n_in = 0;
+    return INFINITY;
+  }
+  for (i = 0; i < n_hits; ++i) {
+    double m[3], u[3], L, best = INFINITY, r;
+    wire_of(g, wire_id[i], m, u, &L);
+    for (j = 0; j + 1 < n; ++j) {
+      double v = orc_seg_wire_dist2(pts + 3 * j, pts + 3 * (j + 1), m, u, L);
+      if (v < best) best = v;
+    }
+    r = sqrt(best) - (double)drift[i];
+    if (r * r < p->lambda_mm2) {
+      E += r * r;
+      ++cnt;
+    } else {
+      E += p->lambda_mm2;
+    }
+  }
+  free(pts); free(s);
+  if (n_in) *n_in = cnt;
+  return E;
+}

@@ -153,6 +153,27 @@ int orc_gn_refine(const orc_geometry *g, const orc_field *f, const orc_params *p
 int orc_neighbour_seed(const orc_field *f, const orc_params *p, const double seed[5], int32_t dir,
                        int32_t max_steps, double out[5]);
 
+/* ---- Adaptive step size (the error-controlled RKN of the propagator section 2.2 cites) ---- */
+typedef struct {
+  double tol_mm;        /* local error bound per step, mm                           */
+  double h_min_mm;      /* smallest step (taken even when the bound is not met)     */
+  double h_max_mm;      /* largest step (bounds the chord's sagitta)                */
+} orc_adaptive;
+
+/* One trial step of size h from (x, T): the RKN result (xn, Tn) and the error
+ * estimate h^2 |k1 - k2 - k3 + k4|. */
+void orc_rkn_trial(const orc_field *f, double Lam, double h, const double x[3], const double T[3],
+                   double xn[3], double Tn[3], double *err);
+/* Accepted positions along a path of length n_steps * step_mm (turn_stop honoured):
+ * pts [n][3] (pts[0] = the seed point), s [n] their arc lengths; returns n (at most
+ * max_pts; 0 if |p| is too small). n_rejected (optional) counts rejected trials. */
+int orc_adaptive_trace(const orc_field *f, const orc_params *p, const orc_adaptive *a, const double seed[5],
+                       int32_t max_pts, double *pts, double *s, int32_t *n_rejected);
+/* Eq. (1) over the chords between consecutive accepted positions (brute force). */
+double orc_score_adaptive(const orc_geometry *g, const orc_field *f, const orc_params *p, const orc_adaptive *a,
+                          const double seed[5], int32_t n_hits, const int32_t *wire_id, const float *drift,
+                          int32_t *n_in, int32_t *n_steps_taken);
+
 #ifdef __cplusplus
 }
 #endif
