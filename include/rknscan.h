@@ -197,6 +197,25 @@ rkn_status rkn_scan_windows_topk(rkn_ctx *ctx, const rkn_scan_params *p, int32_t
                                  const rkn_window *w, int32_t k, int64_t *index, double *score,
                                  double *seeds5);
 
+/* Adaptive step size: the error-controlled RKN of the propagator that section 2.2
+ * cites, in place of the fixed step. A trial step of size h also gives the error
+ * estimate err = h^2 |k1 - k2 - k3 + k4| from its four stage accelerations; it is
+ * accepted when err <= tol_mm or h <= h_min_mm, and the next step is h times
+ * 0.9 (tol/err)^(1/4) clamped to [1/4, 4] and to [h_min_mm, h_max_mm] (a rejected
+ * trial retries shorter). The first trial is h_max_mm; the path has the length of
+ * the fixed-step scan, n_steps * step_mm, its last step cut to end there. h_max_mm
+ * bounds the chord's sagitta h^2 / 8R (0.006 mm at 4 mm and R = 350 mm). */
+typedef struct {
+  double tol_mm, h_min_mm, h_max_mm;
+} rkn_adaptive_params;
+
+/* rkn_scan_windows with the adaptive step size: the scores use the chords between
+ * accepted positions. FP32 only (p->precision 32); 4 trial steps per cull block
+ * (p->block_steps is ignored); turn_stop is honoured. Outputs as rkn_scan_windows. */
+rkn_status rkn_scan_windows_adaptive(rkn_ctx *ctx, const rkn_scan_params *p, const rkn_adaptive_params *ap,
+                                     int32_t n_windows, const rkn_window *w, double *score, int32_t *n_in,
+                                     int64_t *best_index, double *best_score);
+
 /* The same outputs as rkn_scan_windows, computed by the paper's two-kernel form of
  * the scan (section 4.2), kept as an experiment beside the fused kernel: a record
  * kernel stores every seed's position after each step in HBM (12 bytes per seed and

@@ -454,6 +454,33 @@ rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_wind
   return run_scan(c, p, wins, tiles, ev_tiles, total, score, n_in, best_index, best_score);
 }
 
+rkn_status rkn_scan_windows_adaptive(rkn_ctx* c, const rkn_scan_params* p, const rkn_adaptive_params* ap,
+                                     int32_t n_windows, const rkn_window* w, double* score, int32_t* n_in,
+                                     int64_t* best_index, double* best_score) {
+  if (!c) return RKN_E_ARG;
+  rkn_status st = check_scan_params(c, p);
+  if (st != RKN_OK) return st;
+  if ((st = check_state(c)) != RKN_OK) return st;
+  if (p->precision != 32) return arg_err(c, "adaptive scan: precision must be 32");
+  if (!ap || !is_fin(ap->tol_mm) || !(ap->tol_mm > 0) || !is_fin(ap->h_min_mm) || !(ap->h_min_mm > 0) ||
+      !is_fin(ap->h_max_mm) || ap->h_max_mm < ap->h_min_mm ||
+      p->n_steps * p->step_mm / ap->h_min_mm > 1e7)
+    return arg_err(c, "adaptive scan: tol > 0, 0 < h_min <= h_max, path / h_min <= 1e7");
+  rkn_scan_params q = *p;
+  q.block_steps = 4;
+  std::vector<rkn::WindowDev> wins;
+  std::vector<rkn::Tile> tiles;
+  std::vector<int32_t> ev_tiles;
+  int64_t total = 0;
+  if ((st = prepare_windows(c, &q, n_windows, w, wins, tiles, ev_tiles, total, nullptr, nullptr)) != RKN_OK)
+    return st;
+  RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
+  c->adapt = ap;
+  st = run_scan(c, &q, wins, tiles, ev_tiles, total, score, n_in, best_index, best_score);
+  c->adapt = nullptr;
+  return st;
+}
+
 rkn_status rkn_scan_windows_topk(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
                                  int32_t k, int64_t* index, double* score, double* seeds5) {
   if (!c) return RKN_E_ARG;

@@ -205,6 +205,67 @@ __device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, const 
   }
 }
 
+// The same step with the local error estimate of the adaptive step size: err =
+// h^2 |k1 - k2 - k3 + k4| (the stage accelerations agree to O(h^2) for a smooth
+// force). Kept apart from rkn_step so that the fixed-step path carries none of it.
+template <typename R, int FIELD>
+__device__ __forceinline__ void rkn_step_err(State<R>& st, const FieldDev& f, const float2* nodes, R h, R& err) {
+  const R h2 = (R)0.5 * h, hh6 = h * h / (R)6, h6 = h / (R)6;
+  if constexpr (FIELD == 0) {
+    const R a = st.lam * (R)f.bz;
+    const R k1x = a * st.ty, k1y = -a * st.tx;
+    const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y;
+    const R k2x = a * t2y, k2y = -a * t2x;
+    const R t3x = st.tx + h2 * k2x, t3y = st.ty + h2 * k2y;
+    const R k3x = a * t3y, k3y = -a * t3x;
+    const R t4x = st.tx + h * k3x, t4y = st.ty + h * k3y;
+    const R k4x = a * t4y, k4y = -a * t4x;
+    const R ex = k1x - k2x - k3x + k4x, ey = k1y - k2y - k3y + k4y;
+    err = h * h * fsqrt(ex * ex + ey * ey);
+    const R dx = h * st.tx + hh6 * (k1x + k2x + k3x);
+    const R dy = h * st.ty + hh6 * (k1y + k2y + k3y);
+    const R dz = h * st.tz;
+    turn(st.tx, st.ctx, h6 * (k1x + (R)2 * (k2x + k3x) + k4x));
+    turn(st.ty, st.cty, h6 * (k1y + (R)2 * (k2y + k3y) + k4y));
+    advance(st, dx, dy, dz);
+  } else {
+    const R l = st.lam;
+    R bx, by, bz;
+    field_rz(f, nodes, st.x, st.y, st.z, bx, by, bz);
+    const R k1x = l * (st.ty * bz - st.tz * by);
+    const R k1y = l * (st.tz * bx - st.tx * bz);
+    const R k1z = l * (st.tx * by - st.ty * bx);
+    const R hh8 = h * h * (R)0.125;
+    field_rz(f, nodes, st.x + h2 * st.tx + hh8 * k1x, st.y + h2 * st.ty + hh8 * k1y,
+             st.z + h2 * st.tz + hh8 * k1z, bx, by, bz);
+    const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y, t2z = st.tz + h2 * k1z;
+    const R lbx = l * bx, lby = l * by, lbz = l * bz;
+    const R k2x = t2y * lbz - t2z * lby;
+    const R k2y = t2z * lbx - t2x * lbz;
+    const R k2z = t2x * lby - t2y * lbx;
+    const R t3x = st.tx + h2 * k2x, t3y = st.ty + h2 * k2y, t3z = st.tz + h2 * k2z;
+    const R k3x = t3y * lbz - t3z * lby;
+    const R k3y = t3z * lbx - t3x * lbz;
+    const R k3z = t3x * lby - t3y * lbx;
+    const R hh2 = h * h * (R)0.5;
+    field_rz(f, nodes, st.x + h * st.tx + hh2 * k3x, st.y + h * st.ty + hh2 * k3y,
+             st.z + h * st.tz + hh2 * k3z, bx, by, bz);
+    const R t4x = st.tx + h * k3x, t4y = st.ty + h * k3y, t4z = st.tz + h * k3z;
+    const R k4x = l * (t4y * bz - t4z * by);
+    const R k4y = l * (t4z * bx - t4x * bz);
+    const R k4z = l * (t4x * by - t4y * bx);
+    const R ex = k1x - k2x - k3x + k4x, ey = k1y - k2y - k3y + k4y, ez = k1z - k2z - k3z + k4z;
+    err = h * h * fsqrt(ex * ex + ey * ey + ez * ez);
+    const R dx = h * st.tx + hh6 * (k1x + k2x + k3x);
+    const R dy = h * st.ty + hh6 * (k1y + k2y + k3y);
+    const R dz = h * st.tz + hh6 * (k1z + k2z + k3z);
+    turn(st.tx, st.ctx, h6 * (k1x + (R)2 * (k2x + k3x) + k4x));
+    turn(st.ty, st.cty, h6 * (k1y + (R)2 * (k2y + k3y) + k4y));
+    turn(st.tz, st.ctz, h6 * (k1z + (R)2 * (k2z + k3z) + k4z));
+    advance(st, dx, dy, dz);
+  }
+}
+
 // Exact squared distance between the chord p0 + s d (s in [0,1]) and the wire
 // m + t u (|t| <= L, |u| = 1): clamp the chord parameter of the line-line optimum,
 // take the wire's closest parameter for it, and if that leaves [-L, L] clamp it and

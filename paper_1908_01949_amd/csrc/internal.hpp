@@ -101,6 +101,7 @@ struct WinSlot {
 
 struct rkn_ctx {
   int device = 0;
+  const rkn_adaptive_params* adapt = nullptr;   // set during an adaptive-step scan only
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;

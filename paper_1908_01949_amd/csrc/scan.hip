@@ -79,6 +79,9 @@ struct ScanArgs {
   int ckpt, n_ckpt;
   int64_t n_pos;
   int max_hits;
+  // adaptive step size (scan_kernel variant 2): path length, error bound, step range
+  double path_len;
+  float tol, h_min, h_max;
 };
 
 // ---------------------------------------------------------------------------------
@@ -328,7 +331,9 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R, int FIELD, int B, int WAVES, int MODE, bool STOP>
+// VAR 0: fixed steps over the whole path; 1: fixed steps, the track ends with its
+// turn partition; 2: adaptive step size (FP32 scan only), turn_stop as given.
+template <typename R, int FIELD, int B, int WAVES, int MODE, int VAR>
 __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   constexpr int TILE = 64 * WAVES;
   // MODE 0: the scan (score E). MODE 1: the refinement forward pass (FP32 only):
@@ -473,8 +478,12 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     __threadfence_block();
     __syncthreads();
 
-    const int nblocks = (a.n_steps + B - 1) / B;
-    const R Kcull = (R)(0.5 * B * a.h + sqrt(lam) + (double)kCullMargin);
+    constexpr bool STOP = VAR != 0;    // lanes can end before the last block
+    constexpr bool ADAPT = VAR == 2;
+    // adaptive: at most 4 L / h_min + 8 trial steps per lane (every rejection at
+    // least shortens the step, and h_min steps are always taken)
+    const int nblocks = ADAPT ? (int)((4.0 * a.path_len / a.h_min + 8.0 + B - 1) / B) : (a.n_steps + B - 1) / B;
+    const R Kcull = (R)(0.5 * B * (ADAPT ? (double)a.h_max : a.h) + sqrt(lam) + (double)kCullMargin);
     const R sqrt_lam = (R)sqrt(lam);
     // STOP (the end of the turn partition): once a step ends inside r < R0 the
     // lane's state is frozen, so its later chords have zero length at that end point
@@ -482,13 +491,16 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     // and a wave whose lanes are all frozen leaves the loop (unless a tape needs states)
     const R r0sq = (R)(a.R0 * a.R0);
     const bool may_exit = STOP && !(MODE == 1 && a.tape);
+    const bool stop_turn = VAR == 1 || (ADAPT && a.turn_stop);
     bool live = true;
+    R hl = (R)a.h_max, arc = (R)0;              // adaptive: next step and path so far
+    const R path = (R)a.path_len;
     for (int blk = 0; blk < nblocks; ++blk) {
       if constexpr (STOP) {
         if (may_exit && __ballot(live) == 0) break;
       }
       const bool live0 = live;
-      const int nb = min(B, a.n_steps - blk * B);
+      const int nb = ADAPT ? B : min(B, a.n_steps - blk * B);
       const int jc = nb / 2;
       if constexpr (MODE == 1) {
         const int step = blk * B;
@@ -508,12 +520,35 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       R cx = st.x, cy = st.y, cz = st.z;
 #pragma unroll
       for (int j = 1; j <= B; ++j) {
-        if (j <= nb && (!STOP || live)) rkn_step<R, FIELD>(st, a.field, nodes, h);
+        if constexpr (ADAPT) {
+          // one trial step; accepted when its error estimate is within the bound
+          // (or it is the smallest step), else the lane stays and retries shorter
+          if (live) {
+            const R hs = hl < path - arc ? hl : path - arc;
+            State<R> tr = st;
+            R err;
+            rkn_step_err<R, FIELD>(tr, a.field, nodes, hs, err);
+            const bool acc = err <= (R)a.tol || hs <= (R)a.h_min;
+            R g = err > (R)0 ? (R)0.9 * fsqrt(fsqrt((R)a.tol / err)) : (R)4;
+            g = g > (R)4 ? (R)4 : (g < (R)0.25 ? (R)0.25 : g);
+            if (acc) {
+              st = tr;
+              arc += hs;
+              if (hs == hl) hl *= g;   // a cut last step leaves the step size
+              live = arc < path && !(stop_turn && st.x * st.x + st.y * st.y < r0sq);
+            } else {
+              hl = hs * (g < (R)1 ? g : (R)1);
+            }
+            hl = hl > (R)a.h_max ? (R)a.h_max : (hl < (R)a.h_min ? (R)a.h_min : hl);
+          }
+        } else {
+          if (j <= nb && (!STOP || live)) rkn_step<R, FIELD>(st, a.field, nodes, h);
+        }
         pts[(j * 3 + 0) * 64 + lane] = st.x;
         pts[(j * 3 + 1) * 64 + lane] = st.y;
         pts[(j * 3 + 2) * 64 + lane] = st.z;
         const R r2 = st.x * st.x + st.y * st.y;
-        if constexpr (STOP) live = live && !(r2 < r0sq);
+        if constexpr (VAR == 1) live = live && !(r2 < r0sq);
         r2min = r2 < r2min ? r2 : r2min;
         r2max = r2 > r2max ? r2 : r2max;
         if (j == jc) {
@@ -737,9 +772,12 @@ template <typename R, int FIELD, int B, int WAVES>
 static bool shape_fits(const rkn_ctx* c) {
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return false;
-  // both variants (with and without the turn-partition stop) must fit the shape
-  return resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0, false>, 64 * WAVES, smem) >= 1 &&
-         resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0, true>, 64 * WAVES, smem) >= 1;
+  // every variant (fixed steps, turn-partition stop, adaptive) must fit the shape
+  bool ok = resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0, 0>, 64 * WAVES, smem) >= 1 &&
+            resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0, 1>, 64 * WAVES, smem) >= 1;
+  if constexpr (std::is_same<R, float>::value)
+    ok = ok && resident_per_cu(c, (const void*)scan_kernel<R, FIELD, B, WAVES, 0, 2>, 64 * WAVES, smem) >= 1;
+  return ok;
 }
 
 // Waves per workgroup. The FP32 field-map path stages the map in LDS once per
@@ -764,7 +802,9 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   a.sect_bytes = (int)sect_table_bytes(c);
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
-  auto kern = a.turn_stop ? scan_kernel<R, FIELD, B, WAVES, MODE, true> : scan_kernel<R, FIELD, B, WAVES, MODE, false>;
+  auto kern = a.turn_stop ? scan_kernel<R, FIELD, B, WAVES, MODE, 1> : scan_kernel<R, FIELD, B, WAVES, MODE, 0>;
+  if constexpr (MODE == 0 && std::is_same<R, float>::value)
+    if (a.h_max > 0) kern = scan_kernel<R, FIELD, B, WAVES, MODE, 2>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int per_cu = resident_per_cu(c, (const void*)kern, TILE, smem);
@@ -891,6 +931,12 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   a.n_steps = p->n_steps;
   a.turn_stop = p->turn_stop;
   a.score = d_score;
+  if (c->adapt) {   // set only for the adaptive scan entry point's call
+    a.path_len = p->n_steps * p->step_mm;
+    a.tol = (float)c->adapt->tol_mm;
+    a.h_min = (float)c->adapt->h_min_mm;
+    a.h_max = (float)c->adapt->h_max_mm;
+  }
   a.nin = d_nin;
   a.parts = parts.as<ArgminPart>();
   return a;

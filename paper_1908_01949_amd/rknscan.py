@@ -70,6 +70,14 @@ class rkn_turn_params(C.Structure):
 RKN_TURNS_MAX = 16
 
 
+class rkn_adaptive_params(C.Structure):
+    _fields_ = [("tol_mm", C.c_double), ("h_min_mm", C.c_double), ("h_max_mm", C.c_double)]
+
+
+def make_adaptive_params(tol_mm=1e-5, h_min_mm=0.25, h_max_mm=4.0) -> rkn_adaptive_params:
+    return rkn_adaptive_params(tol_mm, h_min_mm, h_max_mm)
+
+
 # Exported symbols and their ctypes signatures (the C header declares the same set).
 _P = C.c_void_p
 _SIGS = {
@@ -106,6 +114,7 @@ _SIGS = {
     "rkn_neighbour_seeds": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, C.c_int32, _P, _P]),
     "rkn_find_turns": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rkn_scan_windows_two_kernel": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
+    "rkn_scan_windows_adaptive": (C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -278,6 +287,15 @@ def rkn_scan_windows_two_kernel(ctx, p: rkn_scan_params, windows, score=None, n_
     w = windows_to_c(windows)
     _check(ctx, load_library().rkn_scan_windows_two_kernel(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
                                                            _ptr(best_index), _ptr(best_score)))
+    return score, n_in, best_index, best_score
+
+
+def rkn_scan_windows_adaptive(ctx, p: rkn_scan_params, ap: rkn_adaptive_params, windows, score=None, n_in=None,
+                              best_index=None, best_score=None):
+    """rkn_scan_windows with the adaptive step size (same outputs)."""
+    w = windows_to_c(windows)
+    _check(ctx, load_library().rkn_scan_windows_adaptive(ctx, C.byref(p), C.byref(ap), len(windows), w, _ptr(score),
+                                                         _ptr(n_in), _ptr(best_index), _ptr(best_score)))
     return score, n_in, best_index, best_score
 
 
