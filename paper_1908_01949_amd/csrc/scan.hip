@@ -488,16 +488,33 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     // STOP (the end of the turn partition): once a step ends inside r < R0 the
     // lane's state is frozen, so its later chords have zero length at that end point
     // and cannot lower any distance; a block that starts frozen is not culled at all,
-    // and a wave whose lanes are all frozen leaves the loop (unless a tape needs states)
+    // and a wave whose lanes are all frozen leaves the loop (after writing the frozen
+    // state into the checkpoints still ahead, when a tape is recorded)
     const R r0sq = (R)(a.R0 * a.R0);
-    const bool may_exit = STOP && !(MODE == 1 && a.tape);
+    const bool may_exit = STOP;
     const bool stop_turn = VAR == 1 || (ADAPT && a.turn_stop);
     bool live = true;
     R hl = (R)a.h_max, arc = (R)0;              // adaptive: next step and path so far
     const R path = (R)a.path_len;
     for (int blk = 0; blk < nblocks; ++blk) {
       if constexpr (STOP) {
-        if (may_exit && __ballot(live) == 0) break;
+        if (may_exit && __ballot(live) == 0) {
+          if constexpr (MODE == 1) {
+            // the remaining checkpoints hold the frozen state (as if stepped on)
+            if (a.tape && in_tile) {
+              const float v13[13] = {(float)st.x, (float)st.y, (float)st.z, (float)st.cx, (float)st.cy, (float)st.cz,
+                                     (float)st.tx, (float)st.ty, (float)st.tz, (float)st.ctx, (float)st.cty,
+                                     (float)st.ctz, (float)st.lam};
+              for (int step = blk * B; step < a.n_steps; step += B) {
+                if (step % a.ckpt != 0) continue;
+                float* tp = a.tape + (size_t)(step / a.ckpt) * 13 * a.n_pos + gidx;
+#pragma unroll
+                for (int q = 0; q < 13; ++q) tp[(size_t)q * a.n_pos] = v13[q];
+              }
+            }
+          }
+          break;
+        }
       }
       const bool live0 = live;
       const int nb = ADAPT ? B : min(B, a.n_steps - blk * B);
