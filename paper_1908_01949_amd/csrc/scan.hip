@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     const R r0sq = (R)(a.R0 * a.R0);
     const bool may_exit = STOP;
     const bool stop_turn = VAR == 1 || (ADAPT && a.turn_stop);
-    bool live = true;
+    bool live = valid;                          // lanes without a seed have no track to end
     R hl = (R)a.h_max, arc = (R)0;              // adaptive: next step and path so far
     const R path = (R)a.path_len;
     for (int blk = 0; blk < nblocks; ++blk) {
