@@ -245,6 +245,9 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
         ms_coarse=round(t_coarse * 1e3, 2), ms_topk=round(t_topk * 1e3, 2), ms_gn=round(t_gn * 1e3, 2),
         ms_rescans=round(t_rounds * 1e3, 2), rescan_seeds=int(seeds_scanned),
         events_per_s_gn=ne / t_a, events_per_s_rescan=ne / t_b, speedup=t_b / t_a,
+        # the coarse scan and the top-k are shared: the refinement stages alone, and the
+        # end-to-end ratio a zero-cost refinement would reach
+        refinement_stage_speedup=t_rounds / t_gn, speedup_bound_shared_coarse=t_b / (t_coarse + t_topk),
         rescan_rounds_mean=float(rounds[has].mean()) if has.any() else 0.0,
         events_reached=int(reached.sum()), events_with_seeds=int(has.sum()),
         phi_gn_mean=float(np.nanmean(phi_gn)), phi_start_mean=float(np.nanmean(gn_phi[:, 0])),
