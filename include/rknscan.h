@@ -360,9 +360,10 @@ typedef struct {
  * partition's seed is predicted from that partition's fitted seed
  * (rkn_neighbour_seeds), a window of count[] seeds with half_width[] around it is
  * scanned over the hits still unclassified (sp's cutoff), and its best seed is
- * fitted at both cutoffs and classifies hits likewise (the earlier side first, then
- * the later one, so no hit gets two partitions). A partition is kept when it
- * classifies at least min_hits hits, else that side ends; an event ends when fewer
+ * fitted at both cutoffs and classifies hits likewise; both sides are classified on
+ * the same hits and the side that classifies more keeps them first, the other keeps
+ * those left (no hit gets two partitions). A partition is kept when it classifies at
+ * least min_hits hits, else that side ends; an event ends when fewer
  * than min_hits hits remain unclassified, both sides have ended or it has max_turns
  * partitions. Outputs (host): hit_turn [total hits] = partition index in the order
  * found, -1 unclassified; n_turns [n_events]; and, unless NULL, per event and

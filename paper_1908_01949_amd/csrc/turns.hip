@@ -10,8 +10,8 @@
 // d)^2 < lambda_c of the best fit and removes them; then, on both sides of the
 // partitions found so far, it predicts the neighbouring partition's seed from the
 // outermost fitted seed, scans a window around the prediction, fits and classifies
-// again, until fewer than min_hits hits are left unclassified or no side finds a
-// partition.
+// again (the side that classifies more hits keeps them first), until fewer than
+// min_hits hits are left unclassified or no side finds a partition.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -310,21 +310,31 @@ rkn_status rkn_find_turns(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
     return rkn_scan_windows_topk(c, &q, (int32_t)w.size(), w.data(), k, idx.data(), scores.data(), best5.data());
   };
 
-  // keep or not the (one per event) fitted candidates: classify the unclassified
-  // hits at the fitted seed, label them, move the side; dir 0 is the first
-  // partition of an event, -1/+1 extend its earlier/later side
-  auto accept = [&](const Cands& cd, int dir) -> rkn_status {
+  // classify the fitted candidates (any rows, any events) at the fine cutoff
+  auto classify_rows = [&](const Cands& cd, std::vector<uint8_t>& mask, std::vector<int32_t>& nin,
+                           int& H) -> rkn_status {
     const int64_t n = (int64_t)cd.size();
+    H = c->max_hits_event > 0 ? c->max_hits_event : 1;
+    mask.assign((size_t)n * H, 0);
+    nin.assign(n, 0);
     if (n == 0) return RKN_OK;
-    const int H = c->max_hits_event > 0 ? c->max_hits_event : 1;
-    std::vector<uint8_t> mask((size_t)n * H);
-    std::vector<int32_t> nin(n);
-    rkn_status st2 = rkn_classify_hits(c, &sc, n, cd.ev.data(), cd.seed.data(), mask.data(), nin.data());
-    if (st2 != RKN_OK) return st2;
-    for (int64_t i = 0; i < n; ++i) {
+    return rkn_classify_hits(c, &sc, n, cd.ev.data(), cd.seed.data(), mask.data(), nin.data());
+  };
+
+  // keep or not the classified candidates, in the given row order: a row's partition is
+  // the hits of its mask still unclassified when its turn comes, kept when there are
+  // at least min_hits of them; dirs[i] 0 is the first partition of an event, -1/+1
+  // extend its earlier/later side
+  auto keep = [&](const Cands& cd, const std::vector<int>& dirs, const std::vector<int64_t>& order,
+                  const std::vector<uint8_t>& mask, int H) {
+    for (int64_t i : order) {
       const int e2 = cd.ev[i];
+      const int dir = dirs[i];
       EventState& es = evs[e2];
-      const int k = nin[i];
+      if (es.done) continue;
+      const uint8_t* m = mask.data() + (size_t)i * H;
+      int k = 0;
+      for (size_t o = 0; o < cur[e2].size(); ++o) k += (m[o] && label[cur[e2][o]] < 0) ? 1 : 0;
       if (k < tp->min_hits) {
         if (dir == 0) es.done = true;
         if (dir < 0) es.lo.alive = false;
@@ -332,9 +342,8 @@ rkn_status rkn_find_turns(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
         continue;
       }
       const int t = es.n_turns++;
-      const uint8_t* m = mask.data() + (size_t)i * H;
       for (size_t o = 0; o < cur[e2].size(); ++o)
-        if (m[o]) label[cur[e2][o]] = t;
+        if (m[o] && label[cur[e2][o]] < 0) label[cur[e2][o]] = t;
       es.remaining -= k;
       const int pos = dir == 0 ? 0 : (dir < 0 ? es.lo.pos - 1 : es.hi.pos + 1);
       const size_t b = (size_t)e2 * T + t;
@@ -355,6 +364,17 @@ rkn_status rkn_find_turns(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
       }
       if (es.remaining < tp->min_hits || es.n_turns >= T) es.done = true;
     }
+  };
+
+  auto accept = [&](const Cands& cd, int dir) -> rkn_status {
+    std::vector<uint8_t> mask;
+    std::vector<int32_t> nin;
+    int H = 1;
+    rkn_status st2 = classify_rows(cd, mask, nin, H);
+    if (st2 != RKN_OK) return st2;
+    std::vector<int64_t> order(cd.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
+    keep(cd, std::vector<int>(cd.size(), dir), order, mask, H);
     return RKN_OK;
   };
 
@@ -456,11 +476,16 @@ rkn_status rkn_find_turns(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
       return st;
     }
   }
-  // ---- neighbouring partitions, one side at a time so that a hit goes to one
-  // partition: predicted seed, window scan over the unclassified hits, fits at the
-  // scan's and the classification cutoffs
+  // ---- neighbouring partitions: on both sides, the predicted seed, a window scan over
+  // the unclassified hits and fits at the scan's and the classification cutoffs; both
+  // sides' candidates are classified on the same hits and, per event, the one that
+  // classifies more of them is kept first, the other keeps what is left (a hit gets
+  // one partition)
   for (int round = 1; round < T; ++round) {
     bool any = false;
+    Cands all;
+    std::vector<int> dirs;
+    bool uploaded = false;
     for (int dir = -1; dir <= 1; dir += 2) {
       std::vector<int> evl;
       std::vector<double> from;
@@ -476,7 +501,10 @@ rkn_status rkn_find_turns(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
       std::vector<double> pred;
       std::vector<int32_t> found;
       if ((st = predict(c, &s1, dir, tp->max_extrap_steps, from, pred, found)) != RKN_OK) break;
-      if ((st = upload_remaining()) != RKN_OK) break;
+      if (!uploaded) {
+        if ((st = upload_remaining()) != RKN_OK) break;
+        uploaded = true;
+      }
       std::vector<rkn_window> w;
       for (size_t i = 0; i < evl.size(); ++i) {
         EventState& es = evs[evl[i]];
@@ -506,9 +534,24 @@ rkn_status rkn_find_turns(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
         }
         cd.add(e2, wi.center, &best5[5 * (size_t)e2]);
       }
-      if ((st = fit(cd, s1)) != RKN_OK || (st = fit(cd, sc)) != RKN_OK || (st = accept(cd, dir)) != RKN_OK) break;
+      if ((st = fit(cd, s1)) != RKN_OK || (st = fit(cd, sc)) != RKN_OK) break;
+      for (size_t i = 0; i < cd.size(); ++i) {
+        all.add(cd.ev[i], &cd.center[5 * i], &cd.seed[5 * i]);
+        dirs.push_back(dir);
+      }
     }
     if (st != RKN_OK || !any) break;
+    std::vector<uint8_t> mask;
+    std::vector<int32_t> nin;
+    int H = 1;
+    if ((st = classify_rows(all, mask, nin, H)) != RKN_OK) break;
+    std::vector<int64_t> order(all.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      if (all.ev[a] != all.ev[b]) return all.ev[a] < all.ev[b];
+      return nin[a] > nin[b];
+    });
+    keep(all, dirs, order, mask, H);
   }
   restore();
   if (st != RKN_OK) return st;
