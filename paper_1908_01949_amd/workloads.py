@@ -23,9 +23,10 @@ BATCH = dict(n_events=512, n_steps=6000, precision=32,
 REFINE = dict(k=8, iters=10, ckpt_every=64, scale=(1.0, 100.0, 100.0, 100.0, 100.0))
 
 # Turn-partition reconstruction (section 2.3) of multi-turn events in the solenoid map:
-# Hough windows of 7 x 13 x 7 x 7 x 13 seeds for the first partition, then windows
-# of 5 x 9 x 5 x 5 x 9 seeds around each predicted neighbour (the rkn_turn_params
-# defaults of the binding), the scan cutoff lambda = 64 mm^2, classification at 4 mm^2.
+# Hough windows of 7 x 13 x 7 x 7 x 13 seeds for the first partition (8 candidates),
+# then windows of 5 x 9 x 5 x 5 x 9 seeds around each predicted neighbour (the
+# rkn_turn_params defaults of the binding), the scan cutoff lambda = 64 mm^2,
+# classification at 4 mm^2.
 TURNS = dict(n_events=128, n_steps=6000, precision=32,
              hough=dict(min_votes=6, max_cand=4, gran=(0.01, 50.0, 2.5, 2.5, 4.0), count=(7, 13, 7, 7, 13),
                         count_max=13))
