@@ -131,15 +131,16 @@ def test_turn_stop_gauss_newton(rk, geo, sfield, orc_s):
     c.close()
 
 
-@pytest.mark.parametrize("kind", ["uniform", "solenoid"])
-def test_find_turns(rk, geo, ufield, sfield, orc_u, orc_s, kind):
+@pytest.mark.parametrize("kind,fine", [("uniform", False), ("solenoid", False), ("solenoid", True)])
+def test_find_turns(rk, geo, ufield, sfield, orc_u, orc_s, kind, fine):
     field, O = (ufield, orc_u) if kind == "uniform" else (sfield, orc_s)
     evs = [synth.event_multi_turn(geo, field, s) for s in range(6)]
     c, off, wid, dr = _ctx(rk, geo, field, evs)
     hp = rk.make_hough_params(b_ref=field.b_ref, min_votes=6, max_cand=4, gran=(0.01, 50.0, 2.5, 2.5, 4.0),
                               count=(7, 13, 7, 7, 13), count_max=13)
     sp = rk.make_scan_params(n_steps=N_STEPS, precision=32)
-    tp = rk.make_turn_params()
+    # fine: the optional (z0, pz0) rescan of the first partition's candidates
+    tp = rk.make_turn_params(fine_count=(31, 25), n_candidates=4) if fine else rk.make_turn_params()
     r = rk.rkn_find_turns(c.ctx, hp, sp, tp, wid.size, len(evs))
     lam_c = tp.lambda_classify_mm2
     prm_c = O.params(n_steps=N_STEPS, turn_stop=1, lambda_mm2=lam_c)
@@ -178,7 +179,7 @@ def test_find_turns(rk, geo, ufield, sfield, orc_u, orc_s, kind):
         _note(f"{kind} event {e}: true turns {np.bincount(x.turn_of[x.turn_of >= 0]).tolist()}, found "
               f"{[(int(pos[t]), int(r['turn_nhits'][e, t])) for t in range(nt)]}, "
               f"eps/pi {[(round(v['eps'], 2), round(v['pi'], 2)) for v in q]}")
-    _note(f"{kind}: mean eps {np.mean(eps):.2f}, mean pi {np.mean(pur):.2f}, {flips} boundary flips")
+    _note(f"{kind} (fine rescan {fine}): mean eps {np.mean(eps):.2f}, mean pi {np.mean(pur):.2f}, {flips} boundary flips")
     # every event finds its first partition mostly within one true turn
     assert np.mean(pur) >= 0.5
     # the context's hits are the caller's again: a plain scan still runs on them
