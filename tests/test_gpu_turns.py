@@ -189,3 +189,31 @@ def test_find_turns(rk, geo, ufield, sfield, orc_u, orc_s, kind, fine):
     osc, _, _, _, _ = O.scan_windows(O.params(n_steps=N_STEPS), off, wid, dr, w)
     pu.check_scores(sc, osc)
     c.close()
+
+
+def test_find_turns_edges_and_errors(rk, geo, sfield):
+    """One partition at most with max_turns = 1; nothing found when min_hits exceeds
+    every event's hits; a small event next to a large one; invalid parameters raise
+    and leave the context's hits as they were."""
+    evs = [synth.event_multi_turn(geo, sfield, 3), synth.event_fixed_total(geo, sfield, 2, n_total=8, noise_frac=0.0)]
+    c, off, wid, dr = _ctx(rk, geo, sfield, evs)
+    hp = rk.make_hough_params(b_ref=sfield.b_ref, min_votes=6, max_cand=4, gran=(0.01, 50.0, 2.5, 2.5, 4.0),
+                              count=(7, 13, 7, 7, 13), count_max=13)
+    sp = rk.make_scan_params(n_steps=N_STEPS, precision=32)
+    r = rk.rkn_find_turns(c.ctx, hp, sp, rk.make_turn_params(max_turns=1), wid.size, 2)
+    assert r["n_turns"][0] == 1 and r["n_turns"][1] == 0
+    lab = r["hit_turn"]
+    assert set(np.unique(lab[off[0]:off[1]])) <= {-1, 0} and np.all(lab[off[1]:off[2]] == -1)
+    r = rk.rkn_find_turns(c.ctx, hp, sp, rk.make_turn_params(min_hits=10000), wid.size, 2)
+    assert np.all(r["n_turns"] == 0) and np.all(r["hit_turn"] == -1)
+    for bad in (dict(max_turns=0), dict(max_turns=17), dict(min_hits=0), dict(lambda_classify_mm2=0.0),
+                dict(n_candidates=0), dict(count=(0, 9, 5, 5, 9)), dict(fine_count=(0, 1))):
+        with pytest.raises(rk.RknError):
+            rk.rkn_find_turns(c.ctx, hp, sp, rk.make_turn_params(**bad), wid.size, 2)
+    with pytest.raises(rk.RknError):
+        rk.rkn_find_turns(c.ctx, hp, rk.make_scan_params(n_steps=N_STEPS, precision=64), rk.make_turn_params(),
+                          wid.size, 2)
+    # the caller's hits are in place: the loop gives the same answer again
+    r2 = rk.rkn_find_turns(c.ctx, hp, sp, rk.make_turn_params(max_turns=1), wid.size, 2)
+    assert np.array_equal(r2["n_turns"], [1, 0])
+    c.close()
