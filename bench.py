@@ -317,6 +317,29 @@ def turns_leg(geo, field, n_events):
     return out
 
 
+def adaptive_batch_leg(ctx, hp, sp, n_events, t_fixed, reps=2):
+    """The same batch with the adaptive step size (error-controlled RKN, tol 1e-5 mm,
+    steps 0.25-4 mm over the same 6000 mm path), planned and replayed like the
+    fixed-step batch; not the headline (its steps are not 1 mm RKN steps)."""
+    import torch
+    ap = rk.make_adaptive_params()
+    rk.rkn_batch_plan_adaptive(ctx.ctx, hp, sp, ap)
+    rk.rkn_batch_launch(ctx.ctx, None, None)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ms_scan = []
+    for _ in range(reps):
+        rk.rkn_batch_launch(ctx.ctx, None, None)
+        ms_scan.append(rk.rkn_batch_info(ctx.ctx)[3])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    out = dict(ms_step=round(dt * 1e3, 1), ms_scan=round(float(np.mean(ms_scan)), 1), events_per_s=n_events / dt,
+               speedup_over_fixed_step=round(t_fixed / dt, 2), tol_mm=ap.tol_mm, h_min_mm=ap.h_min_mm,
+               h_max_mm=ap.h_max_mm)
+    log(f"adaptive batch: {out}")
+    return out
+
+
 def other_workloads(geo, reps=3):
     """The single-event workloads, timed on the GPU (device outputs, inputs resident):
     a 6^5 FP64 scan of a single-turn event, a 16^5 FP32 scan of a multi-turn event
@@ -399,6 +422,7 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the refinement comparison")
     ap.add_argument("--no-other", action="store_true", help="skip the single-event workloads")
     ap.add_argument("--no-bidir", action="store_true", help="skip the two-direction scan")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-step batch")
     ap.add_argument("--turn-events", type=int, default=workloads.TURNS["n_events"],
                     help="multi-turn events of the turn-partition loop (0 = skip)")
     ap.add_argument("--block-steps", type=int, default=0, help="RKN steps per cull block (0 = default)")
@@ -495,6 +519,8 @@ def main():
         log(f"refine: {out['refine']}")
     if not args.no_bidir:
         out["bidirectional"] = bidirectional_leg(ctx, field, sp, ne, dt / args.steps, int(np.diff(off).max()))
+    if not args.no_adaptive:
+        out["adaptive_batch"] = adaptive_batch_leg(ctx, hp, sp, ne, dt / args.steps)
     ctx.close()
     if args.turn_events > 0:
         out["turn_partitions"] = turns_leg(geo, field, args.turn_events)

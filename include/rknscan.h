@@ -265,6 +265,12 @@ rkn_status rkn_batch_plan(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_sc
 rkn_status rkn_batch_autotune(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp,
                               int32_t sample_events, int32_t reps, int32_t *chosen, float *ms);
 
+/* rkn_batch_plan with the adaptive step size of rkn_scan_windows_adaptive (FP32, 4
+ * trial steps per cull block; sp->block_steps ignored): later rkn_batch_launch calls
+ * replay it, and rkn_batch_topk / rkn_batch_results read its scores. */
+rkn_status rkn_batch_plan_adaptive(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp,
+                                   const rkn_adaptive_params *ap);
+
 /* Replay the graphs on the current hits; best_index/best_score per event (global
  * seed index of the batch, -1/+inf for an event without windows) as in
  * rkn_scan_windows. Either may be NULL. */

@@ -238,6 +238,24 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
   return RKN_OK;
 }
 
+rkn_status rkn_batch_plan_adaptive(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan_params* sp,
+                                   const rkn_adaptive_params* ap) {
+  if (!c) return RKN_E_ARG;
+  if (!sp || sp->precision != 32 || !ap || !std::isfinite(ap->tol_mm) || !(ap->tol_mm > 0) ||
+      !std::isfinite(ap->h_min_mm) || !(ap->h_min_mm > 0) || !std::isfinite(ap->h_max_mm) ||
+      ap->h_max_mm < ap->h_min_mm || sp->n_steps * sp->step_mm / ap->h_min_mm > 1e7) {
+    c->err = "batch adaptive: FP32 scan parameters, tol > 0, 0 < h_min <= h_max, path / h_min <= 1e7";
+    return RKN_E_ARG;
+  }
+  rkn_scan_params q = *sp;
+  q.block_steps = 4;
+  // the step-size settings reach the scan's arguments, which the graph captures by value
+  c->adapt = ap;
+  const rkn_status st = rkn_batch_plan(c, hp, &q);
+  c->adapt = nullptr;
+  return st;
+}
+
 rkn_status rkn_batch_autotune(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan_params* sp,
                               int32_t sample_events, int32_t reps, int32_t* chosen, float* ms) {
   if (!c) return RKN_E_ARG;

@@ -115,6 +115,7 @@ _SIGS = {
     "rkn_find_turns": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rkn_scan_windows_two_kernel": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
     "rkn_scan_windows_adaptive": (C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P]),
+    "rkn_batch_plan_adaptive": (C.c_int32, [_P, _P, _P, _P]),
 }
 
 _lib = None
@@ -351,6 +352,10 @@ def rkn_batch_autotune(ctx, hp: rkn_hough_params, sp: rkn_scan_params, sample_ev
     _check(ctx, load_library().rkn_batch_autotune(ctx, C.byref(hp), C.byref(sp), int(sample_events), int(reps),
                                                   C.byref(chosen), ms))
     return chosen.value, list(ms)
+
+
+def rkn_batch_plan_adaptive(ctx, hp: rkn_hough_params, sp: rkn_scan_params, ap) -> None:
+    _check(ctx, load_library().rkn_batch_plan_adaptive(ctx, C.byref(hp), C.byref(sp), C.byref(ap)))
 
 
 def rkn_batch_launch(ctx, best_index=None, best_score=None):

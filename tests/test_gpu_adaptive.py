@@ -77,3 +77,39 @@ def test_adaptive_with_fixed_step_equals_fixed_kernel(rk, geo, sfield):
         with pytest.raises(rk.RknError):
             rk.rkn_scan_windows_adaptive(c.ctx, p, bad, w, a, None, None, None)
     c.close()
+
+
+def test_batch_adaptive_equals_window_scan(rk, geo, sfield, orc_s):
+    """The batched persistent launch with the adaptive step size gives the window scan's
+    adaptive scores (same kernel, captured in the graph), and sampled seeds match the
+    oracle's adaptive score."""
+    from paper_1908_01949_amd import workloads
+    evs = synth.events_batch(geo, sfield, 24, seed=3)
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    hp = rk.make_hough_params(b_ref=sfield.b_ref, **workloads.BATCH["hough"])
+    sp = rk.make_scan_params(n_steps=6000, precision=32)
+    ap = rk.make_adaptive_params()
+    rk.rkn_batch_plan_adaptive(c.ctx, hp, sp, ap)
+    bi = np.zeros(24, np.int64); bs = np.zeros(24)
+    rk.rkn_batch_launch(c.ctx, bi, bs)
+    w, score, nin, ev_seed = rk.rkn_batch_results(c.ctx, 24)
+    n = score.size
+    s2 = np.zeros(n); b2 = np.zeros(24, np.int64); e2 = np.zeros(24)
+    rk.rkn_scan_windows_adaptive(c.ctx, sp, ap, w, s2, None, b2, e2)
+    np.testing.assert_allclose(score, s2, rtol=1e-12, atol=0)
+    assert np.array_equal(bi, b2)
+    g = np.sort(np.random.default_rng(33).choice(n, 48, replace=False))
+    sizes = np.prod(w["count"].astype(np.int64), axis=1)
+    base = np.concatenate([[0], np.cumsum(sizes)])
+    osc = []
+    for k in g:
+        wi = int(np.searchsorted(base, k, side="right") - 1)
+        e = int(w[wi]["event"])
+        s = orc_s.window_seed(w[wi], int(k - base[wi]))
+        osc.append(orc_s.score_adaptive(orc_s.params(n_steps=6000), oracle.OrcAdaptive(1e-5, 0.25, 4.0), s,
+                                        evs[e].wire_id, evs[e].drift)[0])
+    rel = pu.check_scores(score[g], np.array(osc))
+    _note(f"adaptive batch: {n} seeds in {len(w)} windows, equal to the window scan, sample rel error {rel:.2e}")
+    c.close()
