@@ -217,3 +217,36 @@ def test_find_turns_edges_and_errors(rk, geo, sfield):
     r2 = rk.rkn_find_turns(c.ctx, hp, sp, rk.make_turn_params(max_turns=1), wid.size, 2)
     assert np.array_equal(r2["n_turns"], [1, 0])
     c.close()
+
+
+def test_turn_stop_fp64_scan_and_batch(rk, geo, ufield, sfield, orc_u):
+    """The FP64 scan with the stop rule against the oracle (uniform field), and the
+    batched graph with the stop rule equal to the window scan on the batch's windows."""
+    from paper_1908_01949_amd import workloads
+    ev = synth.event_multi_turn(geo, ufield, 4)
+    c, off, wid, dr = _ctx(rk, geo, ufield, [ev])
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], (0.02, 40.0, 2.0, 2.0, 4.0), (3, 4, 3, 3, 4))])
+    n = int(np.prod(w[0]["count"]))
+    p = rk.make_scan_params(n_steps=N_STEPS, precision=64, turn_stop=1)
+    sc = np.zeros(n); nin = np.zeros(n, np.int32); bi = np.zeros(1, np.int64); bs = np.zeros(1)
+    rk.rkn_scan_windows(c.ctx, p, w, sc, nin, bi, bs)
+    osc, onin, _, _, _ = orc_u.scan_windows(orc_u.params(n_steps=N_STEPS, turn_stop=1), off, wid, dr, w)
+    rel = pu.check_scores(sc, osc, rel=1e-9, abs_=1e-9)
+    assert np.array_equal(nin, onin)
+    pu.check_best(bi[0], osc)
+    _note(f"FP64 with the stop rule: {n} seeds, max rel error {rel:.2e}")
+    c.close()
+    evs = synth.events_batch(geo, sfield, 16, seed=4)
+    c, off, wid, dr = _ctx(rk, geo, sfield, evs)
+    hp = rk.make_hough_params(b_ref=sfield.b_ref, **workloads.BATCH["hough"])
+    sp = rk.make_scan_params(n_steps=N_STEPS, precision=32, turn_stop=1)
+    rk.rkn_batch_plan(c.ctx, hp, sp)
+    bi = np.zeros(16, np.int64); bs = np.zeros(16)
+    rk.rkn_batch_launch(c.ctx, bi, bs)
+    wb, score, _, _ = rk.rkn_batch_results(c.ctx, 16)
+    s2 = np.zeros(score.size); b2 = np.zeros(16, np.int64)
+    rk.rkn_scan_windows(c.ctx, sp, wb, s2, None, b2, np.zeros(16))
+    np.testing.assert_allclose(score, s2, rtol=1e-12, atol=0)
+    assert np.array_equal(bi, b2)
+    _note(f"batch with the stop rule: {score.size} seeds equal to the window scan")
+    c.close()
