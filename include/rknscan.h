@@ -210,8 +210,9 @@ typedef struct {
 } rkn_adaptive_params;
 
 /* rkn_scan_windows with the adaptive step size: the scores use the chords between
- * accepted positions. FP32 only (p->precision 32); 4 trial steps per cull block
- * (p->block_steps is ignored); turn_stop is honoured. Outputs as rkn_scan_windows. */
+ * accepted positions. FP32 or FP64 propagation (p->precision); 4 trial steps per cull
+ * block (p->block_steps is ignored); turn_stop is honoured. Outputs as
+ * rkn_scan_windows. */
 rkn_status rkn_scan_windows_adaptive(rkn_ctx *ctx, const rkn_scan_params *p, const rkn_adaptive_params *ap,
                                      int32_t n_windows, const rkn_window *w, double *score, int32_t *n_in,
                                      int64_t *best_index, double *best_score);
@@ -265,9 +266,9 @@ rkn_status rkn_batch_plan(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_sc
 rkn_status rkn_batch_autotune(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp,
                               int32_t sample_events, int32_t reps, int32_t *chosen, float *ms);
 
-/* rkn_batch_plan with the adaptive step size of rkn_scan_windows_adaptive (FP32, 4
- * trial steps per cull block; sp->block_steps ignored): later rkn_batch_launch calls
- * replay it, and rkn_batch_topk / rkn_batch_results read its scores. */
+/* rkn_batch_plan with the adaptive step size of rkn_scan_windows_adaptive (4 trial
+ * steps per cull block; sp->block_steps ignored): later rkn_batch_launch calls replay
+ * it, and rkn_batch_topk / rkn_batch_results read its scores. */
 rkn_status rkn_batch_plan_adaptive(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp,
                                    const rkn_adaptive_params *ap);
 

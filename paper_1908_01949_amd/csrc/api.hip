@@ -461,7 +461,6 @@ rkn_status rkn_scan_windows_adaptive(rkn_ctx* c, const rkn_scan_params* p, const
   rkn_status st = check_scan_params(c, p);
   if (st != RKN_OK) return st;
   if ((st = check_state(c)) != RKN_OK) return st;
-  if (p->precision != 32) return arg_err(c, "adaptive scan: precision must be 32");
   if (!ap || !is_fin(ap->tol_mm) || !(ap->tol_mm > 0) || !is_fin(ap->h_min_mm) || !(ap->h_min_mm > 0) ||
       !is_fin(ap->h_max_mm) || ap->h_max_mm < ap->h_min_mm ||
       p->n_steps * p->step_mm / ap->h_min_mm > 1e7)

@@ -241,10 +241,10 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
 rkn_status rkn_batch_plan_adaptive(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan_params* sp,
                                    const rkn_adaptive_params* ap) {
   if (!c) return RKN_E_ARG;
-  if (!sp || sp->precision != 32 || !ap || !std::isfinite(ap->tol_mm) || !(ap->tol_mm > 0) ||
+  if (!sp || !ap || !std::isfinite(ap->tol_mm) || !(ap->tol_mm > 0) ||
       !std::isfinite(ap->h_min_mm) || !(ap->h_min_mm > 0) || !std::isfinite(ap->h_max_mm) ||
       ap->h_max_mm < ap->h_min_mm || sp->n_steps * sp->step_mm / ap->h_min_mm > 1e7) {
-    c->err = "batch adaptive: FP32 scan parameters, tol > 0, 0 < h_min <= h_max, path / h_min <= 1e7";
+    c->err = "batch adaptive: scan parameters, tol > 0, 0 < h_min <= h_max, path / h_min <= 1e7";
     return RKN_E_ARG;
   }
   rkn_scan_params q = *sp;

@@ -332,7 +332,7 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
 }
 
 // VAR 0: fixed steps over the whole path; 1: fixed steps, the track ends with its
-// turn partition; 2: adaptive step size (FP32 scan only), turn_stop as given.
+// turn partition; 2: adaptive step size (scan mode only), turn_stop as given.
 template <typename R, int FIELD, int B, int WAVES, int MODE, int VAR>
 __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   constexpr int TILE = 64 * WAVES;
@@ -820,7 +820,7 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
   auto kern = a.turn_stop ? scan_kernel<R, FIELD, B, WAVES, MODE, 1> : scan_kernel<R, FIELD, B, WAVES, MODE, 0>;
-  if constexpr (MODE == 0 && std::is_same<R, float>::value)
+  if constexpr (MODE == 0)
     if (a.h_max > 0) kern = scan_kernel<R, FIELD, B, WAVES, MODE, 2>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;

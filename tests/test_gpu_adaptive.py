@@ -58,6 +58,32 @@ def test_adaptive_scan_matches_oracle(rk, geo, ufield, sfield, orc_u, orc_s, kin
     c.close()
 
 
+@pytest.mark.parametrize("kind", ["uniform", "solenoid"])
+def test_adaptive_fp64_matches_oracle(rk, geo, ufield, sfield, orc_u, orc_s, kind):
+    """FP64 propagation with the adaptive step size: the same step decisions as the FP64
+    oracle except at rounding-level ties, so the scores agree to ~1e-9."""
+    field, O = (ufield, orc_u) if kind == "uniform" else (sfield, orc_s)
+    evs = [synth.event_single_turn(geo, field, 0), synth.event_multi_turn(geo, field, 1)]
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(field); c.upload_hits(off, wid, dr)
+    w = synth.make_windows([(0, 0, evs[0].truth_seeds[0], (0.05, 30.0, 3.0, 3.0, 3.0), (3, 3, 3, 3, 3)),
+                            (1, 0, evs[1].truth_seeds[0], (0.01, 20.0, 1.0, 1.0, 2.0), (2, 3, 2, 2, 3))])
+    n = int(sum(int(np.prod(x["count"])) for x in w))
+    p = rk.make_scan_params(n_steps=2000, precision=64)
+    ap = rk.make_adaptive_params()
+    sc = np.zeros(n); nin = np.zeros(n, np.int32); bi = np.zeros(2, np.int64); bs = np.zeros(2)
+    rk.rkn_scan_windows_adaptive(c.ctx, p, ap, w, sc, nin, bi, bs)
+    osc, onin = _orc_scores(O, O.params(n_steps=2000), oracle.OrcAdaptive(1e-5, 0.25, 4.0), evs, w)
+    rel = pu.check_scores(sc, osc, rel=1e-8, abs_=1e-8)
+    pu.check_nin(nin, onin)
+    n0 = int(np.prod(w[0]["count"]))
+    pu.check_best(bi[0], osc[:n0])
+    pu.check_best(bi[1], osc[n0:], offset=n0)
+    _note(f"{kind} FP64 adaptive: {n} seeds, max rel score error vs the oracle {rel:.2e}")
+    c.close()
+
+
 def test_adaptive_with_fixed_step_equals_fixed_kernel(rk, geo, sfield):
     """h_min = h_max = 1 mm: the adaptive kernel takes the fixed steps, so its scores
     equal the fixed-step kernel's to rounding (different block size, same chords)."""
