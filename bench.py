@@ -395,16 +395,16 @@ def other_workloads(geo, reps=3):
             t2 = time.perf_counter() - t
             out[name]["ms_two_kernel"] = round(t2 * 1e3, 3)
             out[name]["fused_speedup_over_two_kernel"] = round(t2 / dt, 2)
-            # the adaptive step size over the same path length (tol 1e-5 mm, steps 0.25-4 mm)
-            ap = rk.make_adaptive_params()
-            rk.rkn_scan_windows_adaptive(c.ctx, p, ap, w, score, None, bi, bs)
-            rk.rkn_synchronize(c.ctx)
-            t = time.perf_counter()
-            rk.rkn_scan_windows_adaptive(c.ctx, p, ap, w, score, None, bi, bs)
-            rk.rkn_synchronize(c.ctx)
-            t3 = time.perf_counter() - t
-            out[name]["ms_adaptive"] = round(t3 * 1e3, 3)
-            out[name]["adaptive_speedup"] = round(dt / t3, 2)
+        # the adaptive step size over the same path length (tol 1e-5 mm, steps 0.25-4 mm)
+        ap = rk.make_adaptive_params()
+        rk.rkn_scan_windows_adaptive(c.ctx, p, ap, w, score, None, bi, bs)
+        rk.rkn_synchronize(c.ctx)
+        t = time.perf_counter()
+        rk.rkn_scan_windows_adaptive(c.ctx, p, ap, w, score, None, bi, bs)
+        rk.rkn_synchronize(c.ctx)
+        t3 = time.perf_counter() - t
+        out[name]["ms_adaptive"] = round(t3 * 1e3, 3)
+        out[name]["adaptive_speedup"] = round(dt / t3, 2)
         log(f"{name}: {out[name]}")
         c.close()
     return out
