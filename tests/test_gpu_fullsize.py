@@ -176,3 +176,78 @@ def test_refine_top8_of_batch_full(rk, batch, orc_s):
     # that for at most 2 of the 12 sampled seeds and print them
     print(f"refine: sampled seeds where the oracle's minimum is lower: {worse}", flush=True)
     assert len(worse) <= 2, worse
+
+
+def test_turn_loop_128_events_sampled(rk, geo, sfield, orc_s):
+    """The turn-partition loop on the bench's 128 multi-turn events: on 12 sampled
+    events every partition's hits are the oracle's classification at its fitted seed
+    over the hits left before it, and a neighbour's window is centred on the oracle's
+    prediction from the partition next to it."""
+    wl = workloads.TURNS
+    evs = synth.events_multi_turn(geo, sfield, wl["n_events"], seed=1, n_steps=wl["n_steps"])
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    hp = rk.make_hough_params(b_ref=sfield.b_ref, **wl["hough"])
+    sp = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    tp = rk.make_turn_params()
+    r = rk.rkn_find_turns(c.ctx, hp, sp, tp, wid.size, len(evs))
+    prm_c = orc_s.params(n_steps=wl["n_steps"], turn_stop=1, lambda_mm2=tp.lambda_classify_mm2)
+    prm = orc_s.params(n_steps=wl["n_steps"])
+    flips = 0
+    for e in np.sort(np.random.default_rng(10).choice(len(evs), 12, replace=False)):
+        x = evs[e]
+        lab = r["hit_turn"][off[e]:off[e + 1]]
+        nt = int(r["n_turns"][e])
+        pos = r["turn_pos"][e, :nt]
+        for t in range(nt):
+            left = (lab < 0) | (lab >= t)
+            om = orc_s.inlier_mask(prm_c, r["turn_seed"][e, t], x.wire_id[left], x.drift[left]).astype(bool)
+            diff = np.nonzero(om != (lab[left] == t))[0]
+            if diff.size:
+                _, res, _ = orc_s.residual_jacobian(prm_c, r["turn_seed"][e, t], x.wire_id[left], x.drift[left],
+                                                    np.ones(int(left.sum()), np.uint8))
+                assert np.all(np.abs(np.abs(res[diff]) - np.sqrt(tp.lambda_classify_mm2)) < 2e-3), (e, t)
+                flips += diff.size
+            if pos[t] != 0:
+                d = 1 if pos[t] > 0 else -1
+                src = int(np.nonzero(pos[:t] == pos[t] - d)[0][0])
+                pred = orc_s.neighbour_seed(prm, r["turn_seed"][e, src], d)
+                np.testing.assert_allclose(r["turn_center"][e, t, 1:], pred[1:], rtol=0, atol=1e-6)
+    print(f"turn loop, 128 events: {int(r['n_turns'].sum())} partitions, 12 events checked, {flips} boundary flips",
+          flush=True)
+    c.close()
+
+
+def test_batch_adaptive_512_sampled(rk, batch, orc_s, sfield):
+    """The 512-event batch planned with the adaptive step size (the bench's adaptive
+    leg): sampled seeds against the oracle's adaptive score."""
+    import oracle
+    wl = workloads.BATCH
+    b = batch
+    c = b["c"]
+    hp = rk.make_hough_params(b_ref=sfield.b_ref, **wl["hough"])
+    sp = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    ap = rk.make_adaptive_params()
+    rk.rkn_batch_plan_adaptive(c.ctx, hp, sp, ap)
+    ne = len(b["evs"])
+    bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+    rk.rkn_batch_launch(c.ctx, bi, bs)
+    w, score, _, ev_seed = rk.rkn_batch_results(c.ctx, ne)
+    assert np.array_equal(w["count"], b["windows"]["count"])
+    g = np.sort(np.random.default_rng(11).choice(score.size, 96, replace=False))
+    sizes = np.prod(w["count"].astype(np.int64), axis=1)
+    base = np.concatenate([[0], np.cumsum(sizes)])
+    oap = oracle.OrcAdaptive(ap.tol_mm, ap.h_min_mm, ap.h_max_mm)
+    osc = []
+    for k in g:
+        wi = int(np.searchsorted(base, k, side="right") - 1)
+        x = b["evs"][int(w[wi]["event"])]
+        s = orc_s.window_seed(w[wi], int(k - base[wi]))
+        osc.append(orc_s.score_adaptive(orc_s.params(n_steps=wl["n_steps"]), oap, s, x.wire_id, x.drift)[0])
+    rel = pu.check_scores(score[g], np.array(osc))
+    for e in range(ne):
+        lo, hi = ev_seed[e], ev_seed[e + 1]
+        if hi > lo:
+            assert bi[e] == lo + int(np.argmin(score[lo:hi]))
+    print(f"adaptive batch, 512 events: max rel score error on 96 sampled seeds {rel:.2e}", flush=True)
