@@ -251,3 +251,36 @@ def test_batch_adaptive_512_sampled(rk, batch, orc_s, sfield):
         if hi > lo:
             assert bi[e] == lo + int(np.argmin(score[lo:hi]))
     print(f"adaptive batch, 512 events: max rel score error on 96 sampled seeds {rel:.2e}", flush=True)
+
+
+def test_two_direction_512_sampled(rk, batch, orc_s, sfield):
+    """The bench's two-direction leg at full size: the exit-side batch (opposite charge)
+    on sampled seeds against the oracle, then N_c of every event's best entrance and
+    exit seeds, sampled events against the oracle's classification."""
+    wl = workloads.BATCH
+    b = batch
+    c = b["c"]
+    ne = len(b["evs"])
+    sp = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    rk.rkn_batch_plan(c.ctx, rk.make_hough_params(b_ref=sfield.b_ref, **wl["hough"]), sp)
+    rk.rkn_batch_launch(c.ctx, None, None)
+    ent_idx, _, ent_s5 = rk.rkn_batch_topk(c.ctx, 1, n_events=ne)
+    sp_x = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"], charge=1.0)
+    rk.rkn_batch_plan(c.ctx, rk.make_hough_params(b_ref=sfield.b_ref, charge=1.0, **wl["hough"]), sp_x)
+    rk.rkn_batch_launch(c.ctx, None, None)
+    w, score, _, _ = rk.rkn_batch_results(c.ctx, ne)
+    prm_x = orc_s.params(n_steps=wl["n_steps"], charge=1.0)
+    g, se, osc, rel = _check_sample(orc_s, prm_x, b["off"], b["wid"], b["dr"], w, score, np.random.default_rng(12), 192)
+    ext_idx, _, ext_s5 = rk.rkn_batch_topk(c.ctx, 1, n_events=ne)
+    ev = np.nonzero((ent_idx[:, 0] >= 0) & (ext_idx[:, 0] >= 0))[0].astype(np.int32)
+    H = int(np.diff(b["off"]).max())
+    m_in, m_out, n_common = rk.rkn_bidirectional_common(c.ctx, sp, ev, ent_s5[ev, 0], ext_s5[ev, 0], H)
+    prm = orc_s.params(n_steps=wl["n_steps"])
+    for q in np.random.default_rng(13).choice(ev.size, 12, replace=False):
+        e = int(ev[q]); x = b["evs"][e]; nh = x.wire_id.size
+        oi = orc_s.inlier_mask(prm, ent_s5[e, 0], x.wire_id, x.drift).astype(bool)
+        oo = orc_s.inlier_mask(prm_x, ext_s5[e, 0], x.wire_id, x.drift).astype(bool)
+        assert abs(int(n_common[q]) - int((oi & oo).sum())) <= 2, (e, n_common[q], int((oi & oo).sum()))
+        assert not m_in[q, nh:].any() and not m_out[q, nh:].any()
+    print(f"two directions, 512 events: exit-side sample rel error {rel:.2e}; {int((n_common >= 20).sum())} of "
+          f"{ev.size} events with N_c >= 20", flush=True)
