@@ -66,6 +66,19 @@ def test_multi_turn_16_5_full(rk, geo, ufield, orc_u):
     g, se, osc, rel = _check_sample(orc_u, prm, off, wid, dr, w, score, np.random.default_rng(5), 384)
     print(f"16^5: max rel score error on {g.size} sampled seeds {rel:.2e}", flush=True)
     _check_best_against_sample(orc_u, prm, off, wid, dr, w, bi, bs, se, osc, [0])
+    # the bench's two-kernel and adaptive forms of the same scan
+    s2 = np.zeros(n); b2 = np.zeros(1, np.int64)
+    rk.rkn_scan_windows_two_kernel(c.ctx, p, w, s2, None, b2, np.zeros(1))
+    np.testing.assert_allclose(s2, score, rtol=2e-6, atol=1e-6)
+    import oracle
+    ap = rk.make_adaptive_params()
+    s3 = np.zeros(n)
+    rk.rkn_scan_windows_adaptive(c.ctx, p, ap, w, s3, None, np.zeros(1, np.int64), np.zeros(1))
+    oap = oracle.OrcAdaptive(ap.tol_mm, ap.h_min_mm, ap.h_max_mm)
+    o3 = np.array([orc_u.score_adaptive(prm, oap, orc_u.window_seed(w[0], int(k)), ev.wire_id, ev.drift)[0]
+                   for k in g[:64]])
+    rel3 = pu.check_scores(s3[g[:64]], o3)
+    print(f"16^5: two-kernel equal to the fused scan to rounding; adaptive sample rel error {rel3:.2e}", flush=True)
     c.close()
 
 
