@@ -440,7 +440,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (events shard across GPUs without any "
-              "exchange; see DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "exchange between them); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
