@@ -439,7 +439,7 @@ def main():
         log(f"copied {args.copy_calibration} MiB three times")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (events shard across GPUs without any "
+        print("bench.py: the scan is measured on one GPU only (events shard across GPUs without any "
               "exchange between them); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
