@@ -207,7 +207,7 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
         (nidx, nsc, ns5), dt = _sync_time(lambda: rk.rkn_scan_windows_topk(ctx.ctx, sp, w, k, n_events=ne))
         t_rounds += dt
         seeds_scanned += len(rows) * 6 ** 5
-        # the k best of this round, each with the step of the grid it came from
+        # the k best of this rescan, each with the step of the grid it came from
         widx = np.zeros(ne, np.int64)
         wsz = 6 ** 5
         first_row = np.full(ne, -1)
