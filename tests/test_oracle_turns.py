@@ -155,3 +155,20 @@ def test_quality_eqs_2_3_hand_example():
     # two found partitions owned by one true partition: the larger share counts
     q = quality.turn_quality(np.array([0, 0, 0, 1]), np.array([0, 1, 1, -1]))
     assert q[0]["found"] == 1 and q[0]["eps"] == pytest.approx(2 / 3) and q[1]["eps"] == 0.0
+
+
+def test_loop_defaults_follow_the_paper():
+    """The turn loop's stop rule and the two-direction cut use the paper's numbers, and
+    the window around a predicted seed spans at least the paper's resolution of the
+    predicted (z0, pz0)."""
+    import json
+    import os
+    from paper_1908_01949_amd import rknscan
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+    tp = rknscan.make_turn_params()
+    assert tp.min_hits == g["stop_unclassified_hits"]["value"]
+    assert tp.half_width[1] >= g["turn_seed_resolution_z0_mm"]["value"]
+    assert tp.half_width[4] >= g["turn_seed_resolution_pz0_MeV"]["value"]
+    import inspect
+    import bench
+    assert inspect.signature(bench.bidirectional_leg).parameters["n_c_min"].default == g["common_hits_cut"]["value"]
