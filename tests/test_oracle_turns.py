@@ -172,3 +172,24 @@ def test_loop_defaults_follow_the_paper():
     import inspect
     import bench
     assert inspect.signature(bench.bidirectional_leg).parameters["n_c_min"].default == g["common_hits_cut"]["value"]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "solenoid"])
+def test_time_reversed_track_retraces_the_curve(geo, ufield, sfield, kind):
+    """The reading of the exit-side scan: a state reversed in direction and propagated
+    with the opposite charge retraces the same curve back to the seed point (the RKN map
+    is time-reversible to its truncation error)."""
+    field = ufield if kind == "uniform" else sfield
+    O = oracle.Oracle(geo, field)
+    rng = np.random.default_rng(15)
+    for _ in range(4):
+        seed = _outward_seed(rng)
+        ok, x0, T0, lam = O.seed_state(O.params(), seed)
+        x, T = x0.copy(), T0.copy()
+        for _ in range(900):
+            x, T = O.rkn_step(lam, 1.0, x, T)
+        xr, Tr = x.copy(), -T
+        for _ in range(900):
+            xr, Tr = O.rkn_step(-lam, 1.0, xr, Tr)
+        assert np.linalg.norm(xr - x0) < 1e-6, np.linalg.norm(xr - x0)
+        assert np.linalg.norm(-Tr - T0) < 1e-9
