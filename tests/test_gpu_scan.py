@@ -297,3 +297,51 @@ def test_argument_errors(rk, geo, ufield, ev1):
     rk.rkn_scan_windows(c.ctx, p, w, *out)
     assert np.isfinite(out[0]).all()
     c.close()
+
+
+@pytest.mark.parametrize("kind", ["uniform", "solenoid"])
+def test_scan_rotation_invariance(rk, geo, ufield, sfield, kind):
+    """Both fields are symmetric about the z axis: rotating every wire and every seed by
+    the same angle about it leaves each seed's score unchanged (up to rounding), for
+    angles that move the event's hits across the azimuth sectors and the -pi/pi seam."""
+    import dataclasses
+    field = ufield if kind == "uniform" else sfield
+    ev = synth.event_fixed_total(geo, field, 3, n_total=120, noise_frac=0.2)
+    off, wid, dr = synth.pack_events([ev])
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], (0.03, 40.0, 3.0, 3.0, 4.0), (3, 3, 3, 3, 3))])
+    n = 243
+    p = rk.make_scan_params(n_steps=6000, precision=32)
+    ref = None
+    for ang in (0.0, 0.7, np.pi - 0.01, 2.9, -1.3):
+        ca, sa = np.cos(ang), np.sin(ang)
+        g2 = dataclasses.replace(geo, mx=ca * geo.mx - sa * geo.my, my=sa * geo.mx + ca * geo.my,
+                                 ux=ca * geo.ux - sa * geo.uy, uy=sa * geo.ux + ca * geo.uy)
+        # explicit seeds: a window's (px, py) grid would not rotate with the seeds
+        seeds = np.array([synth_window_seed(w[0], k) for k in range(n)])
+        rs = seeds.copy()
+        rs[:, 0] = seeds[:, 0] + ang
+        rs[:, 2] = ca * seeds[:, 2] - sa * seeds[:, 3]
+        rs[:, 3] = sa * seeds[:, 2] + ca * seeds[:, 3]
+        c = rk.Context(0)
+        c.upload_geometry(g2); c.upload_field(field); c.upload_hits(off, wid, dr)
+        sc = np.zeros(n); nin = np.zeros(n, np.int32)
+        rk.rkn_scan_seeds(c.ctx, p, np.zeros(n, np.int32), rs, sc, nin, np.zeros(1, np.int64), np.zeros(1))
+        c.close()
+        if ref is None:
+            ref = (sc.copy(), nin.copy())
+            continue
+        np.testing.assert_allclose(sc, ref[0], rtol=2e-5, atol=1e-4)
+        assert np.abs(nin - ref[1]).max() <= 1
+        _note(f"{kind} rotated by {ang:+.2f} rad: max rel score change {np.max(np.abs(sc - ref[0]) / np.maximum(ref[0], 1e-9)):.1e}")
+
+
+def synth_window_seed(win, k):
+    """Seed k of a window's grid (theta slowest, pz fastest), for building explicit seeds."""
+    cnt = [int(x) for x in win["count"]]
+    idx = []
+    for d in range(4, -1, -1):
+        idx.append(k % cnt[d]); k //= cnt[d]
+    idx = idx[::-1]
+    return np.array([win["center"][d] if cnt[d] <= 1 else
+                     win["center"][d] - win["half_width"][d] + 2 * win["half_width"][d] * idx[d] / (cnt[d] - 1)
+                     for d in range(5)])
