@@ -345,3 +345,33 @@ def synth_window_seed(win, k):
     return np.array([win["center"][d] if cnt[d] <= 1 else
                      win["center"][d] - win["half_width"][d] + 2 * win["half_width"][d] * idx[d] / (cnt[d] - 1)
                      for d in range(5)])
+
+
+@pytest.mark.parametrize("kind", ["uniform", "solenoid"])
+def test_scan_z_mirror_invariance(rk, geo, ufield, sfield, kind):
+    """Both fields are mirror-symmetric in z (B_r odd, B_z even): mirroring the wires
+    (u_z -> -u_z, which swaps the stereo signs) and the seeds (z0 -> -z0, pz -> -pz)
+    leaves each seed's score unchanged up to rounding."""
+    import dataclasses
+    field = ufield if kind == "uniform" else sfield
+    ev = synth.event_fixed_total(geo, field, 3, n_total=120, noise_frac=0.2)
+    off, wid, dr = synth.pack_events([ev])
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], (0.03, 40.0, 3.0, 3.0, 4.0), (3, 3, 3, 3, 3))])
+    seeds = np.array([synth_window_seed(w[0], k) for k in range(243)])
+    p = rk.make_scan_params(n_steps=6000, precision=32)
+    out = []
+    for mirror in (False, True):
+        g2 = dataclasses.replace(geo, mz=-geo.mz, uz=-geo.uz) if mirror else geo
+        s2 = seeds.copy()
+        if mirror:
+            s2[:, 1] = -s2[:, 1]
+            s2[:, 4] = -s2[:, 4]
+        c = rk.Context(0)
+        c.upload_geometry(g2); c.upload_field(field); c.upload_hits(off, wid, dr)
+        sc = np.zeros(243); nin = np.zeros(243, np.int32)
+        rk.rkn_scan_seeds(c.ctx, p, np.zeros(243, np.int32), s2, sc, nin, np.zeros(1, np.int64), np.zeros(1))
+        c.close()
+        out.append((sc, nin))
+    np.testing.assert_allclose(out[1][0], out[0][0], rtol=2e-5, atol=1e-4)
+    assert np.abs(out[1][1] - out[0][1]).max() <= 1
+    _note(f"{kind} z-mirror: max rel score change {np.max(np.abs(out[1][0] - out[0][0]) / np.maximum(out[0][0], 1e-9)):.1e}")
