@@ -375,3 +375,28 @@ def test_scan_z_mirror_invariance(rk, geo, ufield, sfield, kind):
     np.testing.assert_allclose(out[1][0], out[0][0], rtol=2e-5, atol=1e-4)
     assert np.abs(out[1][1] - out[0][1]).max() <= 1
     _note(f"{kind} z-mirror: max rel score change {np.max(np.abs(out[1][0] - out[0][0]) / np.maximum(out[0][0], 1e-9)):.1e}")
+
+
+def test_hit_order_invariance(rk, geo, sfield):
+    """The upload sorts each event's hits (layer, twisted azimuth): uploading them in
+    another order gives the same scores (to FP64 summation order) and classification
+    masks that follow the caller's order."""
+    ev = synth.event_fixed_total(geo, sfield, 5, n_total=130, noise_frac=0.2)
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], (0.03, 40.0, 3.0, 3.0, 4.0), (3, 3, 3, 3, 3))])
+    perm = np.random.default_rng(16).permutation(ev.wire_id.size)
+    p = rk.make_scan_params(n_steps=6000, precision=32)
+    res = []
+    for order in (np.arange(ev.wire_id.size), perm):
+        c = rk.Context(0)
+        c.upload_geometry(geo); c.upload_field(sfield)
+        c.upload_hits(np.array([0, order.size], np.int32), ev.wire_id[order], ev.drift[order])
+        sc = np.zeros(243); nin = np.zeros(243, np.int32)
+        rk.rkn_scan_windows(c.ctx, p, w, sc, nin, np.zeros(1, np.int64), np.zeros(1))
+        mask, _ = rk.rkn_classify_hits(c.ctx, p, np.zeros(4, np.int32),
+                                       np.array([synth_window_seed(w[0], k) for k in (0, 60, 121, 242)]), order.size)
+        c.close()
+        res.append((sc, nin, mask))
+    np.testing.assert_allclose(res[1][0], res[0][0], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(res[1][1], res[0][1])
+    assert np.array_equal(res[1][2][:, :perm.size], res[0][2][:, perm])
+    _note("hit order: scores, n_in and masks follow the permutation")
