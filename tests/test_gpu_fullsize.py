@@ -297,3 +297,44 @@ def test_two_direction_512_sampled(rk, batch, orc_s, sfield):
         assert not m_in[q, nh:].any() and not m_out[q, nh:].any()
     print(f"two directions, 512 events: exit-side sample rel error {rel:.2e}; {int((n_common >= 20).sum())} of "
           f"{ev.size} events with N_c >= 20", flush=True)
+
+
+def test_rescan_round_512_full(rk, batch, orc_s, sfield):
+    """One round of the paper's coarse-to-fine comparator at the benchmark's size: 6^5
+    grids around the 8 best seeds of every event (about 4 000 windows, 31 M seeds);
+    the device top-8 per event equals a host sort of all scores by (score, index), and
+    sampled scores match the oracle."""
+    wl = workloads.BATCH
+    b = batch
+    c = b["c"]
+    ne = len(b["evs"])
+    sp = rk.make_scan_params(n_steps=wl["n_steps"], precision=wl["precision"])
+    rk.rkn_batch_plan(c.ctx, rk.make_hough_params(b_ref=sfield.b_ref, **wl["hough"]), sp)
+    rk.rkn_batch_launch(c.ctx, None, None)
+    idx, sc, s5 = rk.rkn_batch_topk(c.ctx, 8, n_events=ne)
+    rows = [(e, j) for e in range(ne) for j in range(8) if idx[e, j] >= 0]
+    w = np.zeros(len(rows), synth.WINDOW_DTYPE)
+    w["event"] = [e for e, _ in rows]
+    w["candidate"] = [j for _, j in rows]
+    w["center"] = [s5[e, j] for e, j in rows]
+    w["half_width"] = (0.005, 10.0, 0.5, 0.5, 1.0)
+    w["count"] = 6
+    tidx, tsc, _ = rk.rkn_scan_windows_topk(c.ctx, sp, w, 8, n_events=ne)
+    n = len(rows) * 6 ** 5
+    score = np.zeros(n)
+    rk.rkn_scan_windows(c.ctx, sp, w, score, None, np.zeros(ne, np.int64), np.zeros(ne))
+    base = 0
+    for e in range(ne):
+        k = int((w["event"] == e).sum()) * 6 ** 5
+        if k == 0:
+            assert np.all(tidx[e] == -1)
+            continue
+        seg = score[base:base + k]
+        order = np.lexsort((np.arange(k), seg))[:8]
+        assert np.array_equal(tidx[e, :order.size], base + order), e
+        np.testing.assert_array_equal(tsc[e, :order.size], seg[order])
+        base += k
+    g, se, osc, rel = _check_sample(orc_s, orc_s.params(n_steps=wl["n_steps"]), b["off"], b["wid"], b["dr"], w, score,
+                                    np.random.default_rng(14), 192)
+    print(f"rescan round, {len(rows)} windows, {n} seeds: device top-8 equal to the host sort; "
+          f"sample rel error {rel:.2e}", flush=True)
