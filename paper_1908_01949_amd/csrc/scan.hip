@@ -485,11 +485,12 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     const int nblocks = ADAPT ? (int)((4.0 * a.path_len / a.h_min + 8.0 + B - 1) / B) : (a.n_steps + B - 1) / B;
     const R Kcull = (R)(0.5 * B * (ADAPT ? (double)a.h_max : a.h) + sqrt(lam) + (double)kCullMargin);
     const R sqrt_lam = (R)sqrt(lam);
-    // STOP (the end of the turn partition): once a step ends inside r < R0 the
-    // lane's state is frozen, so its later chords have zero length at that end point
-    // and cannot lower any distance; a block that starts frozen is not culled at all,
-    // and a wave whose lanes are all frozen leaves the loop (after writing the frozen
-    // state into the checkpoints still ahead, when a tape is recorded)
+    // STOP (a lane's track can end early: at the end of its turn partition, the first
+    // step inside r < R0, or with adaptive steps at the end of the path): from then on
+    // the lane's state is frozen, so its later chords have zero length at that end
+    // point and cannot lower any distance; a block that starts frozen is not culled at
+    // all, and a wave whose lanes are all frozen leaves the loop (after writing the
+    // frozen state into the checkpoints still ahead, when a tape is recorded)
     const R r0sq = (R)(a.R0 * a.R0);
     const bool may_exit = STOP;
     const bool stop_turn = VAR == 1 || (ADAPT && a.turn_stop);
