@@ -5,19 +5,46 @@ and add): the fourth-order Nystrom step (section 2.2) in a uniform field and in 
 distance. Counting choices (negations, per-launch constants, clamps) move a count by
 a few flops, so each is checked to within 3."""
 import math
+
+
 class N:
+    """A number that counts the arithmetic operations applied to it."""
     n = 0
-    def __init__(s, v): s.v = v
-    def _w(s, o): return o if isinstance(o, N) else N(o)
-    def __add__(s, o): N.n += 1; return N(s.v + s._w(o).v)
+
+    def __init__(self, v):
+        self.v = v
+
+    @staticmethod
+    def _w(o):
+        return o if isinstance(o, N) else N(o)
+
+    def __add__(self, o):
+        N.n += 1
+        return N(self.v + self._w(o).v)
+
     __radd__ = __add__
-    def __sub__(s, o): N.n += 1; return N(s.v - s._w(o).v)
-    def __rsub__(s, o): N.n += 1; return N(s._w(o).v - s.v)
-    def __mul__(s, o): N.n += 1; return N(s.v * s._w(o).v)
+
+    def __sub__(self, o):
+        N.n += 1
+        return N(self.v - self._w(o).v)
+
+    def __rsub__(self, o):
+        N.n += 1
+        return N(self._w(o).v - self.v)
+
+    def __mul__(self, o):
+        N.n += 1
+        return N(self.v * self._w(o).v)
+
     __rmul__ = __mul__
-    def __truediv__(s, o): N.n += 1; return N(s.v / s._w(o).v)
-    def __neg__(s): return N(-s.v)
-def sqrt(x): N.n += 1; return N(math.sqrt(x.v))
+
+    def __truediv__(self, o):
+        N.n += 1
+        return N(self.v / self._w(o).v)
+
+    def __neg__(self):
+        return N(-self.v)
+
 
 def rkn_uniform(x, y, z, tx, ty, tz, lam, bz, h):
     h2 = 0.5 * h; hh6 = h * h / 6; h6 = h / 6       # constants per launch, not per step
