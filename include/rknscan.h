@@ -245,14 +245,15 @@ rkn_status rkn_trace(rkn_ctx *ctx, const rkn_scan_params *p, int64_t n_seeds, co
 
 /* ---- Batched scan of every uploaded event ---------------------------------------
  * The Hough stage, the expansion of its windows into seed tiles, one persistent
- * scan launch over all tiles (an atomic work queue of tiles of up to 512 seeds of
- * one window each) and the per-event argmin, captured once as HIP graphs on the
+ * scan launch over all tiles (an atomic work queue of tiles of up to 64 seeds per
+ * wave of the workgroup, 768 with the default shape, of one window each) and the
+ * per-event argmin, captured once as HIP graphs on the
  * context's stream. Re-plan after uploading new hits or geometry. */
 
 /* Validate the parameters, size every buffer for the worst case
  * (n_events x max_cand windows of at most min(max_seeds_window, count_max^5)
  * seeds) and capture the graphs. sp->ptr_flags chooses host or device outputs of
- * rkn_batch_launch. */
+ * rkn_batch_launch. hp and sp must have the same charge and R0 (else RKN_E_ARG). */
 rkn_status rkn_batch_plan(rkn_ctx *ctx, const rkn_hough_params *hp, const rkn_scan_params *sp);
 
 /* Autotuner of the batched path: plans the batch with each block size of
@@ -358,9 +359,10 @@ typedef struct {
  * classification runs with turn_stop on and sp's other settings (sp->precision must
  * be 32). First partition: the Hough windows of all hits (hp), the n_candidates
  * lowest-E seeds of each event (cutoff sp->lambda_mm2); each is fitted by
- * Gauss-Newton (gn_iters, inlier set at sp's cutoff), rescanned over a (z0, pz0) grid
- * of fine_count points within fine_half_width of its fitted values with the rest
- * kept (scored at lambda_classify) and fitted again (inlier set at lambda_classify);
+ * Gauss-Newton (gn_iters, inlier set at sp's cutoff), unless fine_count is (1, 1)
+ * rescanned over a (z0, pz0) grid of fine_count points within fine_half_width of its
+ * fitted values with the rest kept (scored at lambda_classify), and fitted again
+ * (inlier set at lambda_classify);
  * the event keeps the candidate with the lowest E at lambda_classify and classifies
  * the hits with (D - d)^2 < lambda_classify at it; they are removed. Then, on the side
  * before the earliest and after the latest partition found, the neighbouring
@@ -372,7 +374,8 @@ typedef struct {
  * those left (no hit gets two partitions). A partition is kept when it classifies at
  * least min_hits hits, else that side ends; an event ends when fewer
  * than min_hits hits remain unclassified, both sides have ended or it has max_turns
- * partitions. Outputs (host): hit_turn [total hits] = partition index in the order
+ * partitions. hp and sp must have the same charge and R0 (else RKN_E_ARG). Outputs
+ * (host): hit_turn [total hits] = partition index in the order
  * found, -1 unclassified; n_turns [n_events]; and, unless NULL, per event and
  * partition ([n_events][max_turns]): turn_seed [..][5] the fitted seed, turn_center
  * [..][5] the centre of the window its candidate came from (a Hough window for the

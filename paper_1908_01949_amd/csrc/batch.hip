@@ -150,6 +150,10 @@ rkn_status rkn_batch_plan(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
     c->err = "batch: invalid scan parameters";
     return RKN_E_ARG;
   }
+  if (hp->charge != sp->charge || hp->R0 != sp->R0) {
+    c->err = "batch: the Hough and scan parameters must have the same charge and R0";
+    return RKN_E_ARG;
+  }
   if (c->n_wires == 0 || c->field_kind < 0 || c->h_ev_off.empty()) {
     c->err = "batch: upload geometry, field and hits first";
     return RKN_E_STATE;

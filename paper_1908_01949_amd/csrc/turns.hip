@@ -220,6 +220,10 @@ rkn_status rkn_find_turns(rkn_ctx* c, const rkn_hough_params* hp, const rkn_scan
     c->err = "find turns: need hough, FP32 scan and turn parameters and the hit_turn/n_turns outputs";
     return RKN_E_ARG;
   }
+  if (hp->charge != sp->charge || hp->R0 != sp->R0) {
+    c->err = "find turns: the Hough and scan parameters must have the same charge and R0";
+    return RKN_E_ARG;
+  }
   int64_t wsize = 1;
   for (int d = 0; d < 5; ++d) {
     if (tp->count[d] < 1 || !(tp->half_width[d] >= 0) || !std::isfinite(tp->half_width[d]) ||

@@ -213,6 +213,11 @@ def test_find_turns_edges_and_errors(rk, geo, sfield):
     with pytest.raises(rk.RknError):
         rk.rkn_find_turns(c.ctx, hp, rk.make_scan_params(n_steps=N_STEPS, precision=64), rk.make_turn_params(),
                           wid.size, 2)
+    with pytest.raises(rk.RknError):   # Hough and scan charges differ
+        rk.rkn_find_turns(c.ctx, hp, rk.make_scan_params(n_steps=N_STEPS, precision=32, charge=1.0),
+                          rk.make_turn_params(), wid.size, 2)
+    with pytest.raises(rk.RknError):
+        rk.rkn_batch_plan(c.ctx, hp, rk.make_scan_params(n_steps=N_STEPS, precision=32, charge=1.0))
     # the caller's hits are in place: the loop gives the same answer again
     r2 = rk.rkn_find_turns(c.ctx, hp, sp, rk.make_turn_params(max_turns=1), wid.size, 2)
     assert np.array_equal(r2["n_turns"], [1, 0])
