@@ -77,13 +77,17 @@ rkn_status rkn_upload_geometry(rkn_ctx *ctx, int32_t n_wires,
                                int32_t n_layers, const double *layer_rmin,
                                const double *layer_rmax);
 
-/* Uniform solenoid field B = (0, 0, bz_tesla). */
+/* Uniform solenoid field B = (0, 0, bz_tesla). Like every field upload, it drops a
+ * planned batch (rkn_batch_launch then returns RKN_E_STATE until the batch is
+ * planned again) and the refinement state of rkn_refine_setup, both of which were
+ * built for the previous field. */
 rkn_status rkn_upload_field_uniform(rkn_ctx *ctx, double bz_tesla);
 
 /* Axisymmetric field map: B_r and B_z on nodes r_i = r0 + (r1-r0) i/(nr-1),
  * z_j = z0 + (z1-z0) j/(nz-1), arrays [nz][nr] row-major, FP32 tesla. Evaluated by
  * bilinear interpolation in (r, z), clamped to the edge outside the grid;
- * B_x = B_r x/r, B_y = B_r y/r (0 on the axis). nr, nz >= 2. */
+ * B_x = B_r x/r, B_y = B_r y/r (0 on the axis). nr, nz >= 2. Drops a planned
+ * batch and the refinement state, as rkn_upload_field_uniform does. */
 rkn_status rkn_upload_field_rz(rkn_ctx *ctx, int32_t nr, int32_t nz, double r0, double r1,
                                double z0, double z1, const float *br, const float *bz);
 

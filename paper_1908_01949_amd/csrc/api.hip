@@ -216,6 +216,8 @@ rkn_status rkn_upload_field_uniform(rkn_ctx* c, double bz) {
   if (!is_fin(bz)) return arg_err(c, "bz must be finite");
   c->field_kind = 0;
   c->bz = bz;
+  rkn::batch_release(c);   // captured graphs hold the previous field's kind and nodes
+  c->refine_release();     // checkpoints were propagated in the previous field
   return RKN_OK;
 }
 
@@ -243,6 +245,8 @@ rkn_status rkn_upload_field_rz(rkn_ctx* c, int32_t nr, int32_t nz, double r0, do
   c->z0 = z0;
   c->z1 = z1;
   c->bz = 0.0;
+  rkn::batch_release(c);   // captured graphs hold the previous field's kind and nodes
+  c->refine_release();     // checkpoints were propagated in the previous field
   return RKN_OK;
 }
 

@@ -108,6 +108,19 @@ __device__ __forceinline__ void field_rz(const FieldDev& f, const float2* nodes,
   }
 }
 
+// Whether (x, y) lies strictly inside the seed cylinder r < R0 (r0sq = R0^2 in the
+// state's precision): the end of a turn partition. One explicitly fused form, so
+// that every kernel (scan, trace, adjoint recompute) takes the same decision on the
+// same state.
+template <typename R>
+__device__ __forceinline__ bool inside_r0(R x, R y, R r0sq) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_fmaf(x, x, y * y) < r0sq;
+  } else {
+    return __builtin_fma(x, x, y * y) < r0sq;
+  }
+}
+
 // Propagation state. For FP32 the position and the direction carry Kahan
 // compensation terms (the sums of 1 mm increments into ~800 mm positions and of
 // ~3e-3 increments into unit directions would otherwise drift).

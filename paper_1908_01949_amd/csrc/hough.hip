@@ -9,9 +9,12 @@
 //          written out coalesced and the workgroup's maximum folded into the
 //          event maximum with an integer atomic max (order-free).
 //  peaks:  one lane per bin; bins at or above max(min_votes, ceil(max/2)) test their
-//          26 neighbours and survivors are appended to a per-event list.
+//          26 neighbours and survivors are appended to a per-event list (4096
+//          entries; an event with more peaks is resolved by the select stage).
 //  select: one workgroup per event keeps the max_cand best (count desc, flat asc)
-//          and turns each into a window (FP64 geometry, integer counts).
+//          and turns each into a window (FP64 geometry, integer counts); when the
+//          list overflowed it walks the whole accumulator with the peak rule, so the
+//          choice never depends on the order of the list's appends.
 #include <math.h>
 
 #include <algorithm>
@@ -90,19 +93,15 @@ __global__ void hough_zero_kernel(uint32_t* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-__global__ void __launch_bounds__(256)
-hough_peaks_kernel(HoughDev hp, const uint32_t* __restrict__ acc, const uint32_t* __restrict__ ev_max,
-                   int ev0, uint32_t* __restrict__ cand_n, uint2* __restrict__ cand) {
-  const int e = ev0 + blockIdx.y;
-  const long long nb = (long long)hp.n_xy * hp.n_xy * hp.n_r;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nb) return;
-  const uint32_t* A = acc + (size_t)blockIdx.y * nb;
-  const uint32_t c = A[v];
-  uint32_t thr = (ev_max[e] + 1u) / 2u;
+// Peak rule: the bin's count reaches the event's threshold, is >= all 26
+// neighbours and > the neighbours with a smaller flat index.
+__device__ __forceinline__ uint32_t peak_threshold(const HoughDev& hp, uint32_t ev_max) {
+  uint32_t thr = (ev_max + 1u) / 2u;
   if (thr < (uint32_t)hp.min_votes) thr = (uint32_t)hp.min_votes;
-  if (thr < 1u) thr = 1u;
-  if (c < thr) return;
+  return thr < 1u ? 1u : thr;
+}
+
+__device__ __forceinline__ bool beats_neighbours(const HoughDev& hp, const uint32_t* A, long long v, uint32_t c) {
   const int a = (int)(v / ((long long)hp.n_xy * hp.n_r));
   const int b = (int)((v / hp.n_r) % hp.n_xy);
   const int k = (int)(v % hp.n_r);
@@ -114,8 +113,22 @@ hough_peaks_kernel(HoughDev hp, const uint32_t* __restrict__ acc, const uint32_t
         if (aa < 0 || bb < 0 || kk < 0 || aa >= hp.n_xy || bb >= hp.n_xy || kk >= hp.n_r) continue;
         const long long nv = ((long long)aa * hp.n_xy + bb) * hp.n_r + kk;
         const uint32_t o = A[nv];
-        if (o > c || (o == c && nv < v)) return;
+        if (o > c || (o == c && nv < v)) return false;
       }
+  return true;
+}
+
+__global__ void __launch_bounds__(256)
+hough_peaks_kernel(HoughDev hp, const uint32_t* __restrict__ acc, const uint32_t* __restrict__ ev_max,
+                   int ev0, uint32_t* __restrict__ cand_n, uint2* __restrict__ cand) {
+  const int e = ev0 + blockIdx.y;
+  const long long nb = (long long)hp.n_xy * hp.n_xy * hp.n_r;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nb) return;
+  const uint32_t* A = acc + (size_t)blockIdx.y * nb;
+  const uint32_t c = A[v];
+  if (c < peak_threshold(hp, ev_max[e])) return;
+  if (!beats_neighbours(hp, A, v, c)) return;
   const uint32_t slot = atomicAdd(cand_n + e, 1u);
   if (slot < (uint32_t)kCandCap) cand[(size_t)e * kCandCap + slot] = make_uint2(c, (uint32_t)v);
 }
@@ -140,26 +153,47 @@ __device__ int half_max_extent(const HoughDev& hp, const uint32_t* A, int a, int
 }
 
 __global__ void __launch_bounds__(256)
-hough_select_kernel(HoughDev hp, const uint32_t* __restrict__ acc, int ev0,
+hough_select_kernel(HoughDev hp, const uint32_t* __restrict__ acc, const uint32_t* __restrict__ ev_max, int ev0,
                     const uint32_t* __restrict__ cand_n, const uint2* __restrict__ cand,
                     WinSlot* __restrict__ slots, int32_t* __restrict__ n_valid) {
   __shared__ uint2 s_best[kMaxCand];
   __shared__ uint2 s_red[256];
   __shared__ int s_nsel;
   const int e = ev0 + blockIdx.x, tid = threadIdx.x;
+  const long long nbins = (long long)hp.n_xy * hp.n_xy * hp.n_r;
+  const uint32_t* A = acc + (size_t)blockIdx.x * nbins;
+  // More peaks than the list holds: which ones the list kept depends on the order
+  // of the appends, so the selection then walks the whole accumulator with the
+  // peak rule instead (slower, same result as an unbounded list).
+  const bool overflow = cand_n[e] > (uint32_t)kCandCap;
+  const uint32_t thr = peak_threshold(hp, ev_max[e]);
   const int n = (int)min(cand_n[e], (uint32_t)kCandCap);
   const uint2* L = cand + (size_t)e * kCandCap;
   // repeated selection of the best remaining (count desc, flat asc)
   uint2 prev = make_uint2(0xffffffffu, 0u);   // strictly "worse than" this bound
   int nsel = 0;
-  for (int j = 0; j < hp.max_cand && j < n; ++j) {
+  for (int j = 0; j < hp.max_cand && (overflow || j < n); ++j) {
     uint2 best = make_uint2(0u, 0xffffffffu);
     bool have = false;
-    for (int i = tid; i < n; i += 256) {
-      const uint2 x = L[i];
-      const bool after_prev = x.x < prev.x || (x.x == prev.x && x.y > prev.y);
-      if (!after_prev) continue;
-      if (!have || x.x > best.x || (x.x == best.x && x.y < best.y)) {
+    if (!overflow) {
+      for (int i = tid; i < n; i += 256) {
+        const uint2 x = L[i];
+        const bool after_prev = x.x < prev.x || (x.x == prev.x && x.y > prev.y);
+        if (!after_prev) continue;
+        if (!have || x.x > best.x || (x.x == best.x && x.y < best.y)) {
+          best = x;
+          have = true;
+        }
+      }
+    } else {
+      for (long long v = tid; v < nbins; v += 256) {
+        const uint32_t cnt = A[v];
+        if (cnt < thr) continue;
+        const uint2 x = make_uint2(cnt, (uint32_t)v);
+        const bool after_prev = x.x < prev.x || (x.x == prev.x && x.y > prev.y);
+        if (!after_prev) continue;
+        if (have && !(x.x > best.x || (x.x == best.x && x.y < best.y))) continue;
+        if (!beats_neighbours(hp, A, v, cnt)) continue;
         best = x;
         have = true;
       }
@@ -183,7 +217,6 @@ hough_select_kernel(HoughDev hp, const uint32_t* __restrict__ acc, int ev0,
   if (tid == 0) s_nsel = nsel;
   __syncthreads();
   nsel = s_nsel;
-  const uint32_t* A = acc + (size_t)blockIdx.x * ((size_t)hp.n_xy * hp.n_xy * hp.n_r);
   if (tid < nsel) {
     const long long flat = s_best[tid].y;
     const int a = (int)(flat / ((long long)hp.n_xy * hp.n_r));
@@ -341,7 +374,8 @@ static hipError_t run_hough_chunk(rkn_ctx* c, const HoughDev& h, int ev0, int n,
                      acc.as<uint32_t>(), c->hough_max.as<uint32_t>(), ev0, c->hough_cand_n.as<uint32_t>(),
                      c->hough_cand.as<uint2>());
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(hough_select_kernel, dim3(n), dim3(256), 0, c->stream, h, acc.as<uint32_t>(), ev0,
+  hipLaunchKernelGGL(hough_select_kernel, dim3(n), dim3(256), 0, c->stream, h, acc.as<uint32_t>(),
+                     c->hough_max.as<uint32_t>(), ev0,
                      c->hough_cand_n.as<uint32_t>(), c->hough_cand.as<uint2>(), c->hough_slots.as<WinSlot>(),
                      c->hough_nsel.as<int32_t>());
   return hipGetLastError();
@@ -422,23 +456,13 @@ rkn_status rkn_hough_seed_windows(rkn_ctx* c, const rkn_hough_params* hp, int32_
   const int ne = c->n_events;
   std::vector<WinSlot> slots((size_t)kMaxCand * ne);
   std::vector<int32_t> nsel(ne);
-  std::vector<uint32_t> ncand(ne);
   if ((e = queue_hough_all(c, h)) != hipSuccess) return herr(c, e, "hough");
   e = hipMemcpyAsync(slots.data(), c->hough_slots.p, sizeof(WinSlot) * slots.size(), hipMemcpyDeviceToHost,
                      c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(nsel.data(), c->hough_nsel.p, sizeof(int32_t) * ne, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ncand.data(), c->hough_cand_n.p, sizeof(uint32_t) * ne, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return herr(c, e, "hough copy");
-  for (int ev = 0; ev < ne; ++ev) {
-    if (ncand[ev] > (uint32_t)kCandCap) {
-      c->err = "hough: event " + std::to_string(ev) + " has more than " + std::to_string(kCandCap) +
-               " peak candidates; raise min_votes";
-      return RKN_E_CAPACITY;
-    }
-  }
   int32_t n = 0;
   for (int ev = 0; ev < ne; ++ev) {
     int cand = 0;

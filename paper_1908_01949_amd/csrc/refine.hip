@@ -226,6 +226,7 @@ struct BwdArgs {
   FieldDev field;
   int64_t n;                  // seeds (slots)
   int n_steps, ckpt, n_ckpt;
+  int turn_stop;              // 1: the forward pass froze the state at the end of the turn partition
   float h;
   double R0, charge;
   const double* seeds5;       // [n][5]
@@ -322,9 +323,21 @@ __global__ void __launch_bounds__(64) adj_seg_kernel(BwdArgs a) {
     q.lam = lam;
     return q;
   };
+  // With the turn-partition stop the forward pass took a step only while every
+  // earlier step ended outside r < R0 (the seed itself is not tested) and froze the
+  // state after that; steps from first_frozen on leave the state as it is (M = I).
+  const float r0sq = (float)(a.R0 * a.R0);
+  bool live = !(a.turn_stop && k > 0 && inside_r0(s.x, s.y, r0sq));
+  int first_frozen = live ? n1 : n0;
   put(0, s);
   for (int j = 1; j <= n1 - n0; ++j) {
-    rkn_step<float, FIELD>(s, a.field, a.field.nodes, a.h);
+    if (live) {
+      rkn_step<float, FIELD>(s, a.field, a.field.nodes, a.h);
+      if (a.turn_stop && inside_r0(s.x, s.y, r0sq)) {
+        live = false;
+        first_frozen = n0 + j;
+      }
+    }
     put(j, s);
   }
   const int e = a.seed_event[p];
@@ -341,57 +354,67 @@ __global__ void __launch_bounds__(64) adj_seg_kernel(BwdArgs a) {
   for (int q = 0; q < 28; ++q) A[q] = 0.0;
   for (int st = n1 - 1; st >= n0; --st) {
     const State<float> sn = get(st - n0);
+    const bool frozen = st >= first_frozen;
     float M[7][7];
-    step_jacobian<FIELD>(sn, a.field, a.h, M);
-    // Phi <- M^T Phi, a <- M^T a (column by column, in place)
+    if (frozen) {
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      double col[7];
+      for (int r = 0; r < 7; ++r)
 #pragma unroll
-      for (int r = 0; r < 7; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * Phi[q][c];
-        col[r] = acc;
-      }
-#pragma unroll
-      for (int r = 0; r < 7; ++r) Phi[r][c] = col[r];
+        for (int c = 0; c < 7; ++c) M[r][c] = r == c ? 1.0f : 0.0f;
+    } else {
+      step_jacobian<FIELD>(sn, a.field, a.h, M);
     }
-    {
-      double col[7];
-#pragma unroll
-      for (int r = 0; r < 7; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * av[q];
-        col[r] = acc;
-      }
-#pragma unroll
-      for (int r = 0; r < 7; ++r) av[r] = col[r];
-    }
-    if constexpr (WANT_S) {
-      // A <- M^T A M over the upper triangle: B = A M by columns, then (M^T B)
-      double nA[28];
+    // Phi <- M^T Phi, a <- M^T a (column by column, in place); nothing when frozen
+    if (!frozen) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) {
-        double b[7];
+        double col[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) {
           double acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < 7; ++q) acc += A[r <= q ? upper_index(r, q) : upper_index(q, r)] * (double)M[q][c];
-          b[r] = acc;
+          for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * Phi[q][c];
+          col[r] = acc;
         }
 #pragma unroll
-        for (int r = 0; r <= c; ++r) {
+        for (int r = 0; r < 7; ++r) Phi[r][c] = col[r];
+      }
+      {
+        double col[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
           double acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * b[q];
-          nA[upper_index(r, c)] = acc;
+          for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * av[q];
+          col[r] = acc;
         }
-      }
 #pragma unroll
-      for (int q = 0; q < 28; ++q) A[q] = nA[q];
+        for (int r = 0; r < 7; ++r) av[r] = col[r];
+      }
+      if constexpr (WANT_S) {
+        // A <- M^T A M over the upper triangle: B = A M by columns, then (M^T B)
+        double nA[28];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          double b[7];
+#pragma unroll
+          for (int r = 0; r < 7; ++r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) acc += A[r <= q ? upper_index(r, q) : upper_index(q, r)] * (double)M[q][c];
+            b[r] = acc;
+          }
+#pragma unroll
+          for (int r = 0; r <= c; ++r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) acc += (double)M[q][r] * b[q];
+            nA[upper_index(r, c)] = acc;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 28; ++q) A[q] = nA[q];
+      }
     }
     // sources of the hits whose minimum lies on chord st
     for (int li = l0; li < l1; ++li) {
@@ -698,6 +721,7 @@ hipError_t refine_backward(rkn_ctx* c, const float* cgrad, bool want_S) {
   b.n_ckpt = c->r_nckpt;
   b.h = (float)c->r_params.step_mm;
   b.R0 = c->r_params.R0;
+  b.turn_stop = c->r_params.turn_stop;
   b.charge = c->r_params.charge;
   b.seeds5 = c->r_seeds.as<double>();
   b.seed_event = c->r_event.as<int32_t>();

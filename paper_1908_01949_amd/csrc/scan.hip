@@ -354,6 +354,9 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_tiles = a.n_tiles_dev ? (int64_t)*a.n_tiles_dev : a.n_tiles;
+  // longest chord: every point of a block's chords lies within B hmax / 2 of its
+  // middle point, and every point of a chord within hmax / 2 of one of its ends
+  const double hmax = VAR == 2 ? (double)a.h_max : a.h;
   R* pts = s_pts + wave * (B + 1) * 3 * 64;
   uint32_t* items = s_items + wave * kCap;
   Slab* slab = reinterpret_cast<Slab*>(a.mscratch) + (size_t)blockIdx.x * a.slab_stride;
@@ -399,7 +402,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       // rho = d + sqrt(lambda) + margin + B h / 2 of c; then |phi_w - phi_c| <=
       // 2 asin(rho / (2 (r_l - rho))) (radii >= r_l - rho and r_l),
       // |z_w - z_c| <= rho, and phi_w - s_l z_w is within dev_l of the hit's psi.
-      const float rho = a.ev_maxdrift[ev] + (float)sqrt(lam) + kCullMargin + 0.5f * (float)(B * a.h);
+      const float rho = a.ev_maxdrift[ev] + (float)sqrt(lam) + kCullMargin + 0.5f * (float)(B * hmax);
       const float* gpsi = a.hits_phi + hbase;
       for (int l = tid; l < a.n_layers; l += TILE) s_slope[l] = a.layer_twist[(size_t)ev * a.n_layers + l].x;
       for (int q = tid; q < a.n_layers * kSectors; q += TILE) {
@@ -483,7 +486,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     // adaptive: at most 4 L / h_min + 8 trial steps per lane (every rejection at
     // least shortens the step, and h_min steps are always taken)
     const int nblocks = ADAPT ? (int)((4.0 * a.path_len / a.h_min + 8.0 + B - 1) / B) : (a.n_steps + B - 1) / B;
-    const R Kcull = (R)(0.5 * B * (ADAPT ? (double)a.h_max : a.h) + sqrt(lam) + (double)kCullMargin);
+    const R Kcull = (R)(0.5 * B * hmax + sqrt(lam) + (double)kCullMargin);
     const R sqrt_lam = (R)sqrt(lam);
     // STOP (a lane's track can end early: at the end of its turn partition, the first
     // step inside r < R0, or with adaptive steps at the end of the path): from then on
@@ -553,7 +556,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
               st = tr;
               arc += hs;
               if (hs == hl) hl *= g;   // a cut last step leaves the step size
-              live = arc < path && !(stop_turn && st.x * st.x + st.y * st.y < r0sq);
+              live = arc < path && !(stop_turn && inside_r0(st.x, st.y, r0sq));
             } else {
               hl = hs * (g < (R)1 ? g : (R)1);
             }
@@ -566,7 +569,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         pts[(j * 3 + 1) * 64 + lane] = st.y;
         pts[(j * 3 + 2) * 64 + lane] = st.z;
         const R r2 = st.x * st.x + st.y * st.y;
-        if constexpr (VAR == 1) live = live && !(r2 < r0sq);
+        if constexpr (VAR == 1) live = live && !inside_r0(st.x, st.y, r0sq);
         r2min = r2 < r2min ? r2 : r2min;
         r2max = r2 > r2max ? r2 : r2max;
         if (j == jc) {
@@ -575,8 +578,8 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           cz = st.z;
         }
       }
-      // radial range of the block's chords (a chord point is within h/2 of an endpoint)
-      const float rmin = fmaxf((float)fsqrt(r2min) - 0.5f * (float)a.h, 0.0f);
+      // radial range of the block's chords (a chord point is within hmax/2 of an endpoint)
+      const float rmin = fmaxf((float)fsqrt(r2min) - 0.5f * (float)hmax, 0.0f);
       const float rmax = (float)fsqrt(r2max);
       // clamp in float first: fminf/fmaxf map NaN to the bound, so the index is in range
       const int b_lo = (int)fminf(fmaxf(rmin, 0.0f), (float)(kTabBins - 1));
@@ -1033,7 +1036,7 @@ trace_kernel(FieldDev f, double R0, double charge, double hstep, int turn_stop, 
     const int target = steps[k];
     for (; n < target && live; ++n) {
       rkn_step<R, FIELD>(st, f, f.nodes, h);
-      live = !(turn_stop && st.x * st.x + st.y * st.y < r0sq);
+      live = !(turn_stop && inside_r0(st.x, st.y, r0sq));
     }
     o[6 * k + 0] = (double)st.x;
     o[6 * k + 1] = (double)st.y;
