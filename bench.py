@@ -35,11 +35,11 @@ def batch_hough_params(field):
     return rk.make_hough_params(b_ref=field.b_ref, **workloads.BATCH["hough"])
 
 
-def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_steps, lam, seconds, block_steps):
+def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_steps, lam, seconds):
     """The FP64 oracle timed on this host's cores (OpenMP threads) on a bounded random
     sample of the same batch, and on one thread (the paper's serial CPU) on a smaller
-    sample; also counts the pruned algorithm's work for the roofline with the block
-    size the kernel uses."""
+    sample. The oracle runs in its band-pruned mode, whose E is the brute-force E; the
+    (chord, hit) pairs it evaluates per seed-step are the band-rule work count."""
     import ctypes
     import oracle
     gomp = ctypes.CDLL("libgomp.so.1")
@@ -60,13 +60,15 @@ def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_ste
     cores = int(gomp.omp_get_max_threads())
     g, se, seeds = draw(min(64, total))
     t = time.perf_counter()
-    sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1)
+    pairs = []
+    sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1, pairs=pairs)
     dt = time.perf_counter() - t
     n = int(min(total, max(64, 64 * seconds / max(dt, 1e-3))))
     if n > 64:
         g, se, seeds = draw(n)
+        pairs = []
         t = time.perf_counter()
-        sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1)
+        sc, _, _, _ = O.scan_seeds(prm, off, wid, dr, se, seeds, mode=1, pairs=pairs)
         dt = time.perf_counter() - t
     rel = float(np.max(np.abs(gpu_scores[g] - sc) / np.maximum(np.abs(sc), 1e-12)))
     # one thread, on the first seeds of the sample (about a quarter of the time budget)
@@ -76,20 +78,12 @@ def cpu_baseline_leg(geo, field, events, windows, ev_seed_off, gpu_scores, n_ste
     O.scan_seeds(prm, off, wid, dr, se[:m1], seeds[:m1], mode=1)
     dt1 = time.perf_counter() - t
     gomp.omp_set_num_threads(cores)
-    # pruned-algorithm work counts on a sub-sample
-    cull = pairs = 0
-    m = min(64, len(g))
-    for i in range(m):
-        e = int(se[i])
-        _, _, cu, pk = O.score_blocked(prm, seeds[i], wid[off[e]:off[e + 1]], dr[off[e]:off[e + 1]], block_steps)
-        cull += cu; pairs += pk
-    ss = m * n_steps
     return dict(value=len(g) * n_steps / dt, unit="seed-steps/s", cores=cores, kind="oracle",
                 sample=f"{len(g)} seeds drawn uniformly from the {total} of the batch, {n_steps} steps each, "
                        f"FP64 band-pruned oracle, OpenMP over seeds, {dt:.1f} s",
                 value_1_thread=m1 * n_steps / dt1,
                 sample_1_thread=f"the first {m1} seeds of that sample on one thread, {dt1:.1f} s"), \
-        dict(cull_per_step=cull / ss, pairs_per_step=pairs / ss, sample_max_rel_score_err=rel)
+        dict(hbar_c11=pairs[0] / (len(g) * n_steps), sample_max_rel_score_err=rel)
 
 
 def measured_traffic():
@@ -385,6 +379,16 @@ def other_workloads(geo, reps=3):
         dt = (time.perf_counter() - t) / reps
         out[name] = dict(seeds=n, steps=wl["n_steps"], ms_scan=round(dt * 1e3, 3),
                          seed_steps_per_s=n * wl["n_steps"] / dt, hough_ms=round(t_hough * 1e3, 3) or None)
+        # roofline of this scan: the kernel's own count of chord distances (untimed
+        # counting instance) in the same flop model, against the peak of its precision
+        k_steps, _, k_chords = rk.rkn_scan_work_counts(c.ctx, p, w)
+        q = k_chords / k_steps
+        f_alg = flops.per_seed_step(field.kind, q)
+        peak = flops.PEAK_FP64_TFLOPS if wl["precision"] == 64 else flops.PEAK_FP32_TFLOPS
+        ach = f_alg * n * wl["n_steps"] / dt / 1e12
+        out[name]["roofline"] = dict(bound="alu", achieved=round(ach, 3), peak=peak, unit="TFLOP/s",
+                                     frac=round(ach / peak, 4), flops_per_seed_step=round(f_alg, 2),
+                                     q_kernel=round(q, 5))
         if wl["precision"] == 32:
             # the paper's record-then-DCA form of the same scan (section 4.2), for comparison
             rk.rkn_scan_windows_two_kernel(c.ctx, p, w, score, None, bi, bs)
@@ -460,9 +464,17 @@ def main():
     lam = 64.0
     sp = rk.make_scan_params(n_steps=args.rkn_steps, precision=32, lambda_mm2=lam, block_steps=args.block_steps)
     hp = batch_hough_params(field)
+    tune_ms = None
+    if args.block_steps == 0:
+        # untimed: the autotuner times each block size on the first events and leaves
+        # the batch planned with the fastest
+        chosen, tune_ms = rk.rkn_batch_autotune(ctx.ctx, hp, sp)
+        sp.block_steps = chosen
+        log(f"autotune: block sizes 4/6/8 -> {[round(v, 1) for v in tune_ms]} ms on the sample, chose {chosen}")
+    else:
+        rk.rkn_batch_plan(ctx.ctx, hp, sp)
     bsteps, tile = rk.rkn_scan_shape(ctx.ctx, sp)
     log(f"scan shape: {bsteps}-step blocks, {tile} seeds per tile ({tile // 64} waves)")
-    rk.rkn_batch_plan(ctx.ctx, hp, sp)
     ne = args.events
     bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
     for i in range(args.warmup):
@@ -482,23 +494,32 @@ def main():
     log(f"timed {args.steps} steps: {dt * 1e3 / args.steps:.1f} ms/step, {nw} windows, {ns} seeds, "
         f"hough {np.mean(ms_h):.2f} ms, scan {np.mean(ms_s):.2f} ms")
 
+    windows, scores, _, ev_seed_off = rk.rkn_batch_results(ctx.ctx, ne)
+    # untimed: the kernel's counting instance over the same windows gives the chord
+    # distances it evaluates per seed-step (the work the roofline credits)
+    k_steps, k_tests, k_chords = rk.rkn_scan_work_counts(ctx.ctx, sp, windows)
+    q_kernel = k_chords / k_steps
+    log(f"kernel work counts: {k_steps} seed-steps, {k_tests} sphere tests, {k_chords} chord distances "
+        f"(q = {q_kernel:.4f} per seed-step)")
     cpu = None
     work = None
     if not args.no_cpu_baseline:
-        windows, scores, _, ev_seed_off = rk.rkn_batch_results(ctx.ctx, ne)
         cpu, work = cpu_baseline_leg(geo, field, events, windows, ev_seed_off, scores, args.rkn_steps,
-                                     lam, args.cpu_seconds, bsteps)
+                                     lam, args.cpu_seconds)
         log(f"cpu baseline: {cpu}")
-        log(f"work counts: {work}")
-    roof = None
+        log(f"band-rule work and sample parity: {work}")
     bwaves = tile // 64
+    f_alg = flops.per_seed_step("rz", q_kernel)
+    achieved = f_alg * seed_steps / (np.mean(ms_s) * 1e-3) / 1e12
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=flops.PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / flops.PEAK_FP32_TFLOPS, 4), traffic=measured_traffic(),
+                flops_per_seed_step=round(f_alg, 2), q_kernel=round(q_kernel, 5),
+                sphere_tests_per_seed_step=round(k_tests / k_steps, 5),
+                kernel=f"scan_kernel<float, rz field, {bsteps}-step blocks, {bwaves} waves>")
     if work is not None:
-        f_alg = flops.per_seed_step("rz", work["pairs_per_step"])
-        achieved = f_alg * seed_steps / (np.mean(ms_s) * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=round(achieved, 3), peak=flops.PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / flops.PEAK_FP32_TFLOPS, 4), traffic=measured_traffic(),
-                    flops_per_seed_step=round(f_alg, 2),
-                    kernel=f"scan_kernel<float, rz field, {bsteps}-step blocks, {bwaves} waves>")
+        # the band rule's (chord, hit) pairs per seed-step, as the oracle counts them
+        roof["hbar_c11"] = round(work["hbar_c11"], 4)
+        roof["flops_per_seed_step_c11"] = round(flops.per_seed_step("rz", work["hbar_c11"]), 2)
     out = {
         "metric": METRIC, "value": value, "unit": "seed-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
@@ -507,7 +528,8 @@ def main():
                                f"65x129 (r,z) solenoid map, circle-Hough windows (1e3-1e5 seeds/event), "
                                f"{args.rkn_steps} RKN steps of 1 mm, FP64 scores and argmin",
                    "n_events": ne, "n_seeds": int(ns), "n_windows": int(nw), "rkn_steps": args.rkn_steps,
-                   "lambda_mm2": lam, "block_steps": bsteps, "seeds_per_tile": tile},
+                   "lambda_mm2": lam, "block_steps": bsteps, "seeds_per_tile": tile,
+                   "block_steps_autotuned_ms": None if tune_ms is None else [round(v, 2) for v in tune_ms]},
         "events_per_s": ne * args.steps / dt,
         "ms_hough": float(np.mean(ms_h)), "ms_scan": float(np.mean(ms_s)),
         "roofline": roof, "cpu_baseline": cpu,

@@ -183,6 +183,16 @@ rkn_status rkn_scan_windows(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_wi
                             const rkn_window *w, double *score, int32_t *n_in,
                             int64_t *best_index, double *best_score);
 
+/* The work the scan of rkn_scan_windows does on these windows, counted by an
+ * instrumented instance of the same kernel (the timed instances carry no counter):
+ * counts[0] = seed-steps taken, counts[1] = sphere tests made by the cull (a wire's
+ * line against the sphere around a block's middle point), counts[2] = chord/wire
+ * distances evaluated (the DCA update of section 2.2). counts is a host array of 3.
+ * Scores are computed but not returned. Fixed steps over the whole path only:
+ * RKN_E_UNSUPPORTED with turn_stop. */
+rkn_status rkn_scan_work_counts(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_windows,
+                                const rkn_window *w, int64_t *counts);
+
 /* The kernel shape a scan with these parameters uses on the current hits: RKN steps
  * per cull block and seeds per tile (= lanes per workgroup), after the default and
  * the LDS/occupancy fit are resolved (tiles of the batched path and of

@@ -76,8 +76,6 @@ def lib():
         P = C.c_void_p
         _lib.orc_score.restype = C.c_double
         _lib.orc_score.argtypes = [P, P, P, P, C.c_int32, P, P, C.c_int32, P, P]
-        _lib.orc_score_blocked.restype = C.c_double
-        _lib.orc_score_blocked.argtypes = [P, P, P, P, C.c_int32, P, P, C.c_int32, P, P, P]
         _lib.orc_inlier_mask.argtypes = [P, P, P, P, C.c_int32, P, P, P]
         _lib.orc_residual_jacobian.argtypes = [P, P, P, P, C.c_int32, P, P, P, P, P]
         _lib.orc_gn_refine.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int32, P, P, P]
@@ -92,7 +90,7 @@ def lib():
         _lib.orc_scan_windows.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int32, P, C.c_int32,
                                           P, P, P, P, P]
         _lib.orc_scan_seeds.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int64, P, P, P, P, P, P,
-                                        C.c_int32, P, P, P, P]
+                                        C.c_int32, P, P, P, P, P]
         _lib.orc_hough_accumulate.argtypes = [P, P, C.c_int32, P, P]
         _lib.orc_hough_peaks.argtypes = [P, P, C.c_int32, P, P]
         _lib.orc_hough_window.argtypes = [P, P, C.c_int64, P]
@@ -205,15 +203,6 @@ class Oracle:
                             _ptr(w), _ptr(d), mode, C.byref(n_in), C.byref(pairs))
         return E, n_in.value, pairs.value
 
-    def score_blocked(self, prm, seed, wire_id, drift, block=8):
-        """E with the kernel's exact block pruning; returns (E, n_in, cull tests, pairs)."""
-        s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
-        d = np.ascontiguousarray(drift, np.float32)
-        n_in = C.c_int32(); cull = C.c_int64(); pairs = C.c_int64()
-        E = lib().orc_score_blocked(C.byref(self.geo), C.byref(self.field), C.byref(prm), _ptr(s), w.size,
-                                    _ptr(w), _ptr(d), int(block), C.byref(n_in), C.byref(cull), C.byref(pairs))
-        return E, n_in.value, cull.value, pairs.value
-
     # ---- refinement ----------------------------------------------------------------
     def inlier_mask(self, prm, seed, wire_id, drift):
         s = np.ascontiguousarray(seed, np.float64); w = np.ascontiguousarray(wire_id, np.int32)
@@ -267,7 +256,9 @@ class Oracle:
                                _ptr(n_in), _ptr(bi), _ptr(bs), C.byref(pairs))
         return score, n_in, bi, bs, pairs.value
 
-    def scan_seeds(self, prm, ev_off, wire_id, drift, seed_event, seeds5, mode=1):
+    def scan_seeds(self, prm, ev_off, wire_id, drift, seed_event, seeds5, mode=1, pairs=None):
+        """Scores, n_in, per-event best index and score of an explicit seed list; when
+        `pairs` is a list, the number of (chord, hit) pairs evaluated is appended to it."""
         ev_off = np.ascontiguousarray(ev_off, np.int32); wire_id = np.ascontiguousarray(wire_id, np.int32)
         drift = np.ascontiguousarray(drift, np.float32)
         seeds5 = np.atleast_2d(np.asarray(seeds5, np.float64))
@@ -275,9 +266,12 @@ class Oracle:
         se = np.ascontiguousarray(seed_event, np.int32)
         n = seeds5.shape[0]; ne = ev_off.size - 1
         score = np.zeros(n); n_in = np.zeros(n, np.int32); bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+        np_ = C.c_int64()
         lib().orc_scan_seeds(C.byref(self.geo), C.byref(self.field), C.byref(prm), ne, _ptr(ev_off),
                              _ptr(wire_id), _ptr(drift), n, _ptr(se), *[_ptr(c) for c in cols], mode,
-                             _ptr(score), _ptr(n_in), _ptr(bi), _ptr(bs))
+                             _ptr(score), _ptr(n_in), _ptr(bi), _ptr(bs), C.byref(np_))
+        if pairs is not None:
+            pairs.append(np_.value)
         return score, n_in, bi, bs
 
     # ---- Hough -------------------------------------------------------------------

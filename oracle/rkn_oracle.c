@@ -313,93 +313,6 @@ double orc_score(const orc_geometry *g, const orc_field *f, const orc_params *p,
   return E;
 }
 
-/* Block pruning, the rule the GPU kernel applies, for counting its algorithmic
- * work (and pinned bit-identical to brute force): steps are taken in blocks of B;
- * a hit is tested for a block only if its layer band, widened by the event's
- * largest drift + sqrt(lambda) + 1 mm, meets the block's radial range; the test
- * keeps the hit if the line of its wire passes within B h / 2 + sqrt(lambda) +
- * 0.05 mm + d of the block's middle point (every chord point lies within B h / 2
- * of it; the 0.05 mm covers the rounding of that test in FP32); kept hits are
- * compared with each chord of the block. cull counts the tests, pairs the
- * chord/hit distances evaluated.                                               */
-double orc_score_blocked(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
-                         int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t B,
-                         int32_t *n_in, int64_t *cull, int64_t *pairs) {
-  double x[3], T[3], Lam, E = 0.0, dmax = 0.0;
-  double *d2 = (double *)malloc(sizeof(double) * (n_hits > 0 ? n_hits : 1));
-  double (*pts)[3] = (double (*)[3])malloc(sizeof(double) * 3 * (B + 1));
-  double sl = sqrt(p->lambda_mm2), h = p->step_mm;
-  int64_t nc = 0, np = 0;
-  int32_t i, n, j, cnt = 0, ended = 0;
-  for (i = 0; i < n_hits; ++i) {
-    d2[i] = INFINITY;
-    if ((double)drift[i] > dmax) dmax = (double)drift[i];
-  }
-  if (!orc_seed_state(p, seed, x, T, &Lam)) {
-    free(d2);
-    free(pts);
-    if (n_in) *n_in = 0;
-    if (cull) *cull = 0;
-    if (pairs) *pairs = 0;
-    return INFINITY;
-  }
-  for (n = 0; n < p->n_steps && !ended; n += B) {
-    int nb = p->n_steps - n < B ? p->n_steps - n : B;
-    double rmin = INFINITY, rmax = 0.0, D = dmax + sl + 1.0;
-    const double *c;
-    pts[0][0] = x[0]; pts[0][1] = x[1]; pts[0][2] = x[2];
-    /* after the end of a turn partition the block's remaining points stay at the
-     * last one (zero-length chords, which cannot lower any distance) */
-    for (j = 1; j <= nb; ++j) {
-      if (!ended) {
-        orc_rkn_step(f, Lam, h, x, T);
-        ended = turn_ended(p, x);
-      }
-      pts[j][0] = x[0]; pts[j][1] = x[1]; pts[j][2] = x[2];
-    }
-    for (j = 0; j <= nb; ++j) {
-      double r = sqrt(pts[j][0] * pts[j][0] + pts[j][1] * pts[j][1]);
-      if (r < rmin) rmin = r;
-      if (r > rmax) rmax = r;
-    }
-    rmin -= 0.5 * h;
-    c = pts[nb / 2];
-    for (i = 0; i < n_hits; ++i) {
-      double m[3], u[3], L, r0, r1, r2, t, dl2, thr;
-      int32_t w = wire_id[i], l = g->layer_of[w];
-      if (rmax < g->layer_rmin[l] - D || rmin > g->layer_rmax[l] + D) continue;
-      ++nc;
-      wire_of(g, w, m, u, &L);
-      r0 = c[0] - m[0]; r1 = c[1] - m[1]; r2 = c[2] - m[2];
-      t = r0 * u[0] + r1 * u[1] + r2 * u[2];
-      dl2 = r0 * r0 + r1 * r1 + r2 * r2 - t * t;
-      thr = 0.5 * B * h + sl + 0.05 + (double)drift[i];
-      if (dl2 > thr * thr) continue;
-      for (j = 0; j < nb; ++j) {
-        double v = orc_seg_wire_dist2(pts[j], pts[j + 1], m, u, L);
-        ++np;
-        if (v < d2[i]) d2[i] = v;
-      }
-    }
-  }
-  for (i = 0; i < n_hits; ++i) {
-    double r = sqrt(d2[i]) - (double)drift[i];
-    double tq = r * r;
-    if (tq < p->lambda_mm2) {
-      E += tq;
-      ++cnt;
-    } else {
-      E += p->lambda_mm2;
-    }
-  }
-  free(d2);
-  free(pts);
-  if (n_in) *n_in = cnt;
-  if (cull) *cull = nc;
-  if (pairs) *pairs = np;
-  return E;
-}
-
 /* Seed grids: per dimension an inclusive linspace c - w + 2 w k / (n - 1)
  * (n = 1 gives c); flat index with theta slowest and pz fastest.             */
 void orc_window_seed(const orc_window *w, int64_t flat, double seed[5]) {
@@ -471,21 +384,25 @@ int orc_scan_seeds(const orc_geometry *g, const orc_field *f, const orc_params *
                    int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
                    int64_t n_seeds, const int32_t *seed_event, const double *theta, const double *z,
                    const double *px, const double *py, const double *pz, int32_t mode,
-                   double *score, int32_t *n_in, int64_t *best_index, double *best_score) {
-  int64_t s;
+                   double *score, int32_t *n_in, int64_t *best_index, double *best_score,
+                   int64_t *pairs_total) {
+  int64_t s, ptot = 0;
   int32_t e;
   for (e = 0; e < n_events; ++e) {
     best_index[e] = -1;
     best_score[e] = INFINITY;
   }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(+ : ptot)
   for (s = 0; s < n_seeds; ++s) {
     int32_t ev = seed_event[s], ni = 0;
+    int64_t np = 0;
     double seed[5] = {theta[s], z[s], px[s], py[s], pz[s]};
     score[s] = orc_score(g, f, p, seed, ev_off[ev + 1] - ev_off[ev], wire_id + ev_off[ev],
-                         drift + ev_off[ev], mode, &ni, NULL);
+                         drift + ev_off[ev], mode, &ni, &np);
     if (n_in) n_in[s] = ni;
+    ptot += np;
   }
+  if (pairs_total) *pairs_total = ptot;
   for (s = 0; s < n_seeds; ++s) {
     int32_t ev = seed_event[s];
     if (best_index[ev] < 0 || score[s] < best_score[ev]) {

@@ -80,12 +80,6 @@ double orc_score(const orc_geometry *g, const orc_field *f, const orc_params *p,
                  int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t mode,
                  int32_t *n_in, int64_t *pairs);
 
-/* The same score with the GPU kernel's two-level exact pruning in blocks of B
- * steps; cull = sphere tests made, pairs = chord/hit distances evaluated. */
-double orc_score_blocked(const orc_geometry *g, const orc_field *f, const orc_params *p, const double seed[5],
-                         int32_t n_hits, const int32_t *wire_id, const float *drift, int32_t B,
-                         int32_t *n_in, int64_t *cull, int64_t *pairs);
-
 /* Seed grid: flat index (theta slowest, pz fastest) -> seed. */
 void orc_window_seed(const orc_window *w, int64_t flat, double seed[5]);
 
@@ -96,12 +90,15 @@ int orc_scan_windows(const orc_geometry *g, const orc_field *f, const orc_params
                      double *score, int32_t *n_in, int64_t *best_index, double *best_score,
                      int64_t *pairs_total);
 
-/* Scan an explicit list of seeds (SoA). best_* are per event, indices into the list. */
+/* Scan an explicit list of seeds (SoA). best_* are per event, indices into the list
+ * (lowest E, ties to the lowest index). pairs_total (optional) receives the number
+ * of (chord, hit) pairs evaluated over all seeds. */
 int orc_scan_seeds(const orc_geometry *g, const orc_field *f, const orc_params *p,
                    int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
                    int64_t n_seeds, const int32_t *seed_event, const double *theta, const double *z,
                    const double *px, const double *py, const double *pz, int32_t mode,
-                   double *score, int32_t *n_in, int64_t *best_index, double *best_score);
+                   double *score, int32_t *n_in, int64_t *best_index, double *best_score,
+                   int64_t *pairs_total);
 
 /* ---- Section 2.1: circle Hough transform over the wire (x, y) positions ---- */
 typedef struct {

@@ -137,7 +137,7 @@ void rkn_destroy(rkn_ctx* c) {
                     &c->hough_cand_n, &c->hough_cand, &c->hough_slots, &c->hough_nsel, &c->hits_orig, &c->hits_phi, &c->layer_ext,
                     &c->sel_seg, &c->sel_win, &c->sel_idx, &c->sel_sc, &c->sel_seed, &c->cl_seeds,
                     &c->cl_perm, &c->cl_tiles, &c->cl_resid, &c->cl_argmin, &c->cl_phi, &c->cl_mask,
-                    &c->cl_count};
+                    &c->cl_count, &c->work_counts};
   for (DevBuf* b : bufs) b->release();
   for (DevBuf& b : c->extra) b.release();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -456,6 +456,41 @@ rkn_status rkn_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_wind
     return st;
   RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
   return run_scan(c, p, wins, tiles, ev_tiles, total, score, n_in, best_index, best_score);
+}
+
+rkn_status rkn_scan_work_counts(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
+                                int64_t* counts) {
+  if (!c) return RKN_E_ARG;
+  rkn_status st = check_scan_params(c, p);
+  if (st != RKN_OK) return st;
+  if ((st = check_state(c)) != RKN_OK) return st;
+  if (!counts) return arg_err(c, "counts must not be NULL");
+  if (p->turn_stop) {
+    c->err = "work counts: fixed steps over the whole path only (turn_stop = 0)";
+    return RKN_E_UNSUPPORTED;
+  }
+  std::vector<rkn::WindowDev> wins;
+  std::vector<rkn::Tile> tiles;
+  std::vector<int32_t> ev_tiles;
+  int64_t total = 0;
+  if ((st = prepare_windows(c, p, n_windows, w, wins, tiles, ev_tiles, total, nullptr, nullptr)) != RKN_OK)
+    return st;
+  RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
+  RKN_HIP(c->work_counts.ensure(4 * sizeof(unsigned long long)), "alloc");
+  const unsigned long long zero[4] = {0, 0, 0, 0};
+  RKN_HIP(hipMemcpyAsync(c->work_counts.p, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream), "counter reset");
+  std::vector<int64_t> bi((size_t)std::max(c->n_events, 1));
+  std::vector<double> bs((size_t)std::max(c->n_events, 1));
+  rkn_scan_params q = *p;
+  q.ptr_flags = 0;
+  c->count_work = c->work_counts.as<unsigned long long>();
+  st = run_scan(c, &q, wins, tiles, ev_tiles, total, nullptr, nullptr, bi.data(), bs.data());
+  c->count_work = nullptr;
+  if (st != RKN_OK) return st;
+  unsigned long long h[4];
+  RKN_HIP(hipMemcpy(h, c->work_counts.p, sizeof(h), hipMemcpyDeviceToHost), "counter copy");
+  for (int k = 0; k < 3; ++k) counts[k] = (int64_t)h[k];
+  return RKN_OK;
 }
 
 rkn_status rkn_scan_windows_adaptive(rkn_ctx* c, const rkn_scan_params* p, const rkn_adaptive_params* ap,

@@ -102,6 +102,7 @@ struct WinSlot {
 struct rkn_ctx {
   int device = 0;
   const rkn_adaptive_params* adapt = nullptr;   // set during an adaptive-step scan only
+  unsigned long long* count_work = nullptr;     // device counters, set during rkn_scan_work_counts only
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -143,6 +144,7 @@ struct rkn_ctx {
   rkn::DevBuf windows, tiles, ev_tiles, parts, counter, mscratch, out_score, out_nin, out_best_i,
       out_best_e, trace_buf, seeds_buf, perm_buf;
   rkn::DevBuf sel_seg, sel_win, sel_idx, sel_sc, sel_seed;   // per-event top-k selection
+  rkn::DevBuf work_counts;                                   // rkn_scan_work_counts
   rkn::DevBuf cl_seeds, cl_perm, cl_tiles, cl_resid, cl_argmin, cl_phi, cl_mask, cl_count;   // classification
   std::vector<rkn::DevBuf> extra;
 

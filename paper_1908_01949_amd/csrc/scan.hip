@@ -19,8 +19,12 @@
 //     groups): exact chord/wire distance of the B chords, the minimum folded into the
 //     seed's running minimum (a per-workgroup slab [hit][lane] in HBM, updated with an
 //     integer atomic min on the non-negative float bit pattern: order-free and
-//     deterministic);
-//   * after the last block each lane forms E = sum min((D - d)^2, lambda) in FP64.
+//     deterministic); a per-wave LDS bitmap marks the (wave, hit) rows that received
+//     a minimum in the current tile;
+//   * after the last block each lane forms E = sum min((D - d)^2, lambda) in FP64,
+//     reading only the marked rows (the others still hold +inf) and resetting them to
+//     +inf, so the slab is written once per workgroup at launch and afterwards only
+//     where a tile touched it.
 // Every filter is exact: a pair it drops can only have a distance above
 // d + sqrt(lambda), where the term is lambda whatever the distance is.
 #include <type_traits>
@@ -36,6 +40,7 @@ constexpr int kTabBins = 1024;     // 1 mm radial bins, the last one open-ended
 constexpr float kBandMargin = 1.0f;   // radial band table
 constexpr float kCullMargin = 0.05f;  // sphere test: covers FP32 rounding of the test (~1e-2 mm)
 constexpr int kSectors = 64;          // twisted-azimuth sectors of the candidate table
+constexpr int kTouchWords = (RKN_MAX_HITS_PER_EVENT + 31) / 32;   // per-wave row bitmap
 constexpr float kPi = 3.14159265358979f;
 
 struct ScanArgs {
@@ -82,6 +87,9 @@ struct ScanArgs {
   // adaptive step size (scan_kernel variant 2): path length, error bound, step range
   double path_len;
   float tol, h_min, h_max;
+  // work counters of the counting instance (COUNT): seed-steps taken, sphere tests
+  // made, chord/wire distances evaluated
+  unsigned long long* work;
 };
 
 // ---------------------------------------------------------------------------------
@@ -243,8 +251,10 @@ __device__ __forceinline__ R load_coherent(const R* p) {
 // the scan, a block whose minimum is not below (d + sqrt(lambda))^2 cannot change
 // the hit's term (it stays lambda unless another block comes closer), so it is not
 // written. The refinement pass writes every block (its inlier set is fixed).
+// The wave's row of the hit is marked in its LDS bitmap.
 template <typename R, int TILE, int MODE, typename S>
-__device__ __forceinline__ void fold_min(S* slab, int hh, int wave, int s, R d2, int chord, R lim2) {
+__device__ __forceinline__ void fold_min(S* slab, uint32_t* touch, int hh, int wave, int s, R d2, int chord,
+                                         R lim2) {
   if constexpr (MODE == 0) {
     if (!(d2 < lim2)) return;
     atomic_min_nonneg(slab + (size_t)hh * TILE + wave * 64 + s, d2);
@@ -254,6 +264,7 @@ __device__ __forceinline__ void fold_min(S* slab, int hh, int wave, int s, R d2,
         ((unsigned long long)__float_as_uint((float)d2) << 32) | (unsigned long long)(unsigned)chord;
     atomicMin(reinterpret_cast<unsigned long long*>(slab + (size_t)hh * TILE + wave * 64 + s), key);
   }
+  atomicOr(touch + (hh >> 5), 1u << (hh & 31));
 }
 
 // Dense pass over a wave's work list: item = (lane << 16) | hit. Full groups of 64
@@ -263,8 +274,8 @@ __device__ __forceinline__ void fold_min(S* slab, int hh, int wave, int s, R d2,
 // the G lanes, so the tail pass costs about B / G chords instead of B.
 template <typename R, int B, int TILE, int MODE, typename S>
 __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, const R* pts,
-                                            const HitRec<R>* s_hits, S* slab, int wave, int lane,
-                                            int nb, int step0, R sqrt_lam) {
+                                            const HitRec<R>* s_hits, S* slab, uint32_t* touch, int wave,
+                                            int lane, int nb, int step0, R sqrt_lam) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -292,7 +303,7 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
       }
     }
     const R lim = w.drift + sqrt_lam;
-    fold_min<R, TILE, MODE>(slab, hh, wave, s, dmin, step0 + jmin, lim * lim);
+    fold_min<R, TILE, MODE>(slab, touch, hh, wave, s, dmin, step0 + jmin, lim * lim);
   }
   const int n_rem = n_items - done;
   if (n_rem > 0) {
@@ -323,7 +334,7 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
     }
     if (act && sub == 0) {
       const R lim = w.drift + sqrt_lam;
-      fold_min<R, TILE, MODE>(slab, hh, wave, s, dmin, step0 + jmin, lim * lim);
+      fold_min<R, TILE, MODE>(slab, touch, hh, wave, s, dmin, step0 + jmin, lim * lim);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -333,7 +344,9 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
 
 // VAR 0: fixed steps over the whole path; 1: fixed steps, the track ends with its
 // turn partition; 2: adaptive step size (scan mode only), turn_stop as given.
-template <typename R, int FIELD, int B, int WAVES, int MODE, int VAR>
+// COUNT: the instance that also counts its work (seed-steps, sphere tests, chord
+// distances) into a.work; the timed instances leave it out.
+template <typename R, int FIELD, int B, int WAVES, int MODE, int VAR, bool COUNT = false>
 __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   constexpr int TILE = 64 * WAVES;
   // MODE 0: the scan (score E). MODE 1: the refinement forward pass (FP32 only):
@@ -351,6 +364,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   __shared__ int s_tile;
   __shared__ double s_red_e[WAVES];
   __shared__ long long s_red_i[WAVES];
+  __shared__ uint32_t s_touch[WAVES][kTouchWords];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_tiles = a.n_tiles_dev ? (int64_t)*a.n_tiles_dev : a.n_tiles;
@@ -360,6 +374,17 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   R* pts = s_pts + wave * (B + 1) * 3 * 64;
   uint32_t* items = s_items + wave * kCap;
   Slab* slab = reinterpret_cast<Slab*>(a.mscratch) + (size_t)blockIdx.x * a.slab_stride;
+  uint32_t* touch = s_touch[wave];
+  unsigned long long w_steps = 0, w_tests = 0, w_chords = 0;   // COUNT only
+  // every slab entry holds "no minimum yet" between tiles: written here once, then
+  // reset by the tile that read it
+  for (int64_t i = tid; i < a.slab_stride; i += TILE) {
+    if constexpr (MODE == 0)
+      slab[i] = (R)INFINITY;
+    else
+      slab[i] = 0xffffffffffffffffULL;
+  }
+  __threadfence_block();
   const R h = (R)a.h;
   const double lam = a.lambda;
   int cur_event = -1;
@@ -472,13 +497,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       st.cx = st.cy = st.cz = (R)0;
       st.ctx = st.cty = st.ctz = (R)0;
     }
-    for (int i = 0; i < nh; ++i) {
-      if constexpr (MODE == 0)
-        slab[(size_t)i * TILE + tid] = (R)INFINITY;
-      else
-        slab[(size_t)i * TILE + tid] = 0xffffffffffffffffULL;
-    }
-    __threadfence_block();
+    if (lane < kTouchWords) touch[lane] = 0u;
     __syncthreads();
 
     constexpr bool STOP = VAR != 0;    // lanes can end before the last block
@@ -611,18 +630,25 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
           const R thr = Kcull + w.drift;
           const bool pass = act && (d2 <= thr * thr);
+          if constexpr (COUNT) {
+            w_tests += act ? 1 : 0;
+            w_chords += pass ? nb : 0;
+          }
           const uint64_t m = __ballot(pass);
           if (m) {
             if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
             n_items += (int)__popcll(m);
             if (n_items > kCap - 64) {
-              flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B, sqrt_lam);
+              flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, touch, wave, lane, nb, blk * B,
+                                            sqrt_lam);
               n_items = 0;
             }
           }
         }
       }
-      if (n_items) flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, wave, lane, nb, blk * B, sqrt_lam);
+      if (n_items)
+        flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, touch, wave, lane, nb, blk * B, sqrt_lam);
+      if constexpr (COUNT) w_steps += (valid && (!STOP || live0)) ? nb : 0;
     }
     __threadfence();
 
@@ -635,7 +661,11 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         int32_t* arow = a.argmin_step + (size_t)gidx * a.max_hits;
         double ph = 0.0;
         for (int i = 0; i < nh; ++i) {
-          const unsigned long long key = load_coherent(slab + (size_t)i * TILE + tid);
+          unsigned long long key = 0xffffffffffffffffULL;
+          if ((touch[i >> 5] >> (i & 31)) & 1u) {
+            key = load_coherent(slab + (size_t)i * TILE + tid);
+            slab[(size_t)i * TILE + tid] = 0xffffffffffffffffULL;
+          }
           // no block came within the cull reach: the distance is beyond it (+inf here)
           const float d2 = key == 0xffffffffffffffffULL ? INFINITY : __uint_as_float((unsigned)(key >> 32));
           const double r = sqrt((double)d2) - (double)s_hits[i].drift;
@@ -657,16 +687,25 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           arow[i] = -1;
         }
         a.phi[gidx] = valid ? ph : INFINITY;
+      } else {
+        for (int i = 0; i < nh; ++i)
+          if ((touch[i >> 5] >> (i & 31)) & 1u) slab[(size_t)i * TILE + tid] = 0xffffffffffffffffULL;
       }
+      __threadfence_block();
       __syncthreads();
       continue;
     }
     // ---- score (Eq. 1), in FP64 ---------------------------------------------------
     double E = 0.0;
     int cnt = 0;
-    if (valid) {
-      for (int i = 0; i < nh; ++i) {
-        const R m2 = load_coherent(slab + (size_t)i * TILE + tid);
+    for (int i = 0; i < nh; ++i) {
+      // rows without a mark were not written in this tile: +inf, nothing to reset
+      R m2 = (R)INFINITY;
+      if ((touch[i >> 5] >> (i & 31)) & 1u) {
+        m2 = load_coherent(slab + (size_t)i * TILE + tid);
+        slab[(size_t)i * TILE + tid] = (R)INFINITY;
+      }
+      if (valid) {
         const double r = sqrt((double)m2) - (double)s_hits[i].drift;
         const double tq = r * r;
         if (tq < lam) {
@@ -676,9 +715,9 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           E += lam;
         }
       }
-    } else {
-      E = INFINITY;
     }
+    if (!valid) E = INFINITY;
+    __threadfence_block();   // the resets land before the next tile's minima
     long long idx = in_tile ? (long long)gidx : (long long)0x7fffffffffffffffLL;
     if (in_tile) {
       if (a.score) a.score[gidx] = E;
@@ -710,6 +749,11 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       a.parts[ti].idx = idx;
     }
     __syncthreads();
+  }
+  if constexpr (COUNT) {
+    atomicAdd(a.work + 0, w_steps);
+    atomicAdd(a.work + 1, w_tests);
+    atomicAdd(a.work + 2, w_chords);
   }
 }
 
@@ -824,8 +868,10 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
   auto kern = a.turn_stop ? scan_kernel<R, FIELD, B, WAVES, MODE, 1> : scan_kernel<R, FIELD, B, WAVES, MODE, 0>;
-  if constexpr (MODE == 0)
+  if constexpr (MODE == 0) {
     if (a.h_max > 0) kern = scan_kernel<R, FIELD, B, WAVES, MODE, 2>;
+    if (a.work) kern = scan_kernel<R, FIELD, B, WAVES, MODE, 0, true>;   // fixed steps only (checked by the caller)
+  }
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int per_cu = resident_per_cu(c, (const void*)kern, TILE, smem);
@@ -960,6 +1006,7 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   }
   a.nin = d_nin;
   a.parts = parts.as<ArgminPart>();
+  a.work = c->count_work;
   return a;
 }
 

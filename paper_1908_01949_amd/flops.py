@@ -11,10 +11,13 @@ the FP64 score sum are not credited.
   F_RKN_GRID     one general RKN4 step (127) + three field evaluations:       220
   F_DOCA         exact squared chord/wire distance:                           50
 
-Per seed-step:  F_alg = F_RKN + F_DOCA * q, where q (chord/hit distances per
-seed-step) is counted by the oracle's block-pruned score on a sample of the same
-workload (the sphere rule the kernel applies; exact: its E equals the brute-force E
-bit for bit).
+Per seed-step:  F_alg = F_RKN + F_DOCA * q, where q is the number of chord/wire
+distances per seed-step that the kernel evaluates on the same workload, counted by
+the kernel's own counting instance (rkn_scan_work_counts; the timed instances carry
+no counter). The cull rule behind q is exact: Eq. 1 over the pairs it keeps equals
+the brute-force score bit for bit (checked on the CPU). The radial band rule alone
+would keep far more pairs (h-bar, counted by the oracle's band-pruned mode); crediting
+those would credit work the kernel never does.
 """
 F_RKN_UNIFORM = 44
 F_FIELD = 31

@@ -104,6 +104,7 @@ _SIGS = {
     "rkn_batch_autotune": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     "rkn_scan_windows_topk": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, _P, _P, _P]),
     "rkn_scan_shape": (C.c_int32, [_P, _P, _P, _P]),
+    "rkn_scan_work_counts": (C.c_int32, [_P, _P, C.c_int32, _P, _P]),
     "rkn_classify_hits": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P]),
     "rkn_bidirectional_common": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, _P]),
     "rkn_refine_setup": (C.c_int32, [_P, _P, C.c_int64, _P, _P, C.c_int32]),
@@ -280,6 +281,15 @@ def rkn_scan_windows(ctx, p: rkn_scan_params, windows, score=None, n_in=None, be
     _check(ctx, load_library().rkn_scan_windows(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
                                                 _ptr(best_index), _ptr(best_score)))
     return score, n_in, best_index, best_score
+
+
+def rkn_scan_work_counts(ctx, p: rkn_scan_params, windows):
+    """(seed-steps, sphere tests, chord distances) of the scan of these windows, from
+    the kernel's counting instance."""
+    w = windows_to_c(windows)
+    counts = np.zeros(3, np.int64)
+    _check(ctx, load_library().rkn_scan_work_counts(ctx, C.byref(p), len(windows), w, _ptr(counts)))
+    return tuple(int(v) for v in counts)
 
 
 def rkn_scan_windows_two_kernel(ctx, p: rkn_scan_params, windows, score=None, n_in=None, best_index=None,

@@ -81,6 +81,14 @@ def test_batch_requires_plan_and_reupload_invalidates(rk, geo, ufield):
     with pytest.raises(rk.RknError) as e:
         rk.rkn_batch_launch(c.ctx, np.zeros(1, np.int64), np.zeros(1))
     assert e.value.status == rk.RKN_E_STATE
+    # a field upload after the plan drops it too (the captured graphs hold the field)
+    for fld in (synth.solenoid_field(), ufield):
+        rk.rkn_batch_plan(c.ctx, rk.make_hough_params(count=(2, 2, 2, 2, 2), count_max=2),
+                          rk.make_scan_params(n_steps=300))
+        c.upload_field(fld)
+        with pytest.raises(rk.RknError) as e:
+            rk.rkn_batch_launch(c.ctx, np.zeros(1, np.int64), np.zeros(1))
+        assert e.value.status == rk.RKN_E_STATE
     c.close()
 
 

@@ -73,3 +73,34 @@ def test_hough_param_errors(rk, geo, ufield, events):
             rk.rkn_hough_seed_windows(c.ctx, rk.make_hough_params(**bad))
         assert e.value.status == rk.RKN_E_ARG
     c.close()
+
+
+def test_candidate_overflow_matches_oracle_eager_and_batched(rk, geo, sfield, orc_s):
+    """An event of 512 noise hits with a low vote floor has more peaks (5475) than the
+    GPU's per-event candidate list holds (4096): the selection then walks the whole
+    accumulator, so the eager and the batched (graph-captured) Hough stages both give
+    the oracle's windows, next to an ordinary event."""
+    noisy = synth.event_fixed_total(geo, sfield, 5, n_total=512, noise_frac=1.0)
+    calm = synth.event_fixed_total(geo, sfield, 1, n_total=150, noise_frac=0.2)
+    evs = [calm, noisy]
+    off, wid, dr = synth.pack_events(evs)
+    kw = dict(b_ref=sfield.b_ref, min_votes=1, max_cand=8, count=(2, 2, 2, 2, 2), count_max=2)
+    ohp = orc_s.hough_params(**kw)
+    acc = orc_s.hough_accumulate(ohp, noisy.wire_id)
+    flats, _ = orc_s.hough_peaks(ohp, acc, 100000)
+    print(f"noisy event: {len(flats)} peaks", flush=True)
+    assert len(flats) > 4096
+    o = orc_s.hough_seed_windows(ohp, off, wid)
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    hp = rk.make_hough_params(**kw)
+    g = rk.rkn_hough_seed_windows(c.ctx, hp)
+    assert len(g) == len(o) and np.array_equal(g["event"], o["event"])
+    assert np.array_equal(g["count"], o["count"])
+    np.testing.assert_allclose(g["center"], o["center"], rtol=0, atol=1e-11)
+    rk.rkn_batch_plan(c.ctx, hp, rk.make_scan_params(n_steps=200, precision=32))
+    bi = np.zeros(2, np.int64); bs = np.zeros(2)
+    rk.rkn_batch_launch(c.ctx, bi, bs)
+    w, _, _, _ = rk.rkn_batch_results(c.ctx, 2)
+    assert np.array_equal(w, g)
+    c.close()

@@ -46,13 +46,13 @@ def _seeds(evs, per_event, rng):
     return np.array(ev, np.int32), np.array(s5)
 
 
-def _setup(rk, geo, field, kind, per_event=4, seed=0):
+def _setup(rk, geo, field, kind, per_event=4, seed=0, turn_stop=0):
     evs = _events(geo, field, kind)
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(field); c.upload_hits(off, wid, dr)
     ev, s5 = _seeds(evs, per_event, np.random.default_rng(seed))
-    sp = rk.make_scan_params(n_steps=N_STEPS, precision=32)
+    sp = rk.make_scan_params(n_steps=N_STEPS, precision=32, turn_stop=turn_stop)
     rk.rkn_refine_setup(c.ctx, sp, ev, s5, ckpt_every=64)
     H = int(np.diff(off).max())
     return c, evs, off, ev, s5, H
@@ -102,12 +102,15 @@ def test_residuals_match_oracle(rk, geo, ufield, sfield, kind):
     c.close()
 
 
-@pytest.mark.parametrize("kind", ["uniform", "solenoid"])
-def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind):
+@pytest.mark.parametrize("kind,turn_stop", [("uniform", 0), ("solenoid", 0), ("uniform", 1), ("solenoid", 1)])
+def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind, turn_stop):
+    """With turn_stop the forward pass freezes each track at the end of its turn
+    partition and the backward sweep recomputes the same frozen steps (identity step
+    Jacobians); the oracle stops its sensitivities there too."""
     field = ufield if kind == "uniform" else sfield
     O = _orc(geo, field)
-    prm = O.params(n_steps=N_STEPS)
-    c, evs, off, ev, s5, H = _setup(rk, geo, field, kind, seed=1)
+    prm = O.params(n_steps=N_STEPS, turn_stop=turn_stop)
+    c, evs, off, ev, s5, H = _setup(rk, geo, field, kind, seed=1, turn_stop=turn_stop)
     n = ev.size
     resid, phi = _forward(rk, c, n, H)
     g = np.zeros((n, 5)); A = np.zeros((n, 5, 5)); jtr = np.zeros((n, 5))
@@ -139,7 +142,8 @@ def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind):
         assert ea < DER_REL, (p, ea)
         assert ec < DER_REL, (p, ec)
         assert eg < tol_g, (p, eg, tol_g)
-    print(f"{kind}: J^T J rel {werr_a:.2e}, J^T c rel {werr_c:.2e}, grad err/tol {werr_g:.2e}", flush=True)
+    print(f"{kind} turn_stop={turn_stop}: J^T J rel {werr_a:.2e}, J^T c rel {werr_c:.2e}, "
+          f"grad err/tol {werr_g:.2e}", flush=True)
     c.close()
 
 

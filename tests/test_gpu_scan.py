@@ -77,16 +77,17 @@ def test_trace_parity(rk, ctx_u, ctx_s, orc_u, orc_s, fieldname, prec, tol):
 # ---------------------------------------------------------------------------------------
 # scans
 # ---------------------------------------------------------------------------------------
-def _scan_both(rk, ctx, O, ev_list, windows, n_steps, prec, lam=64.0, block_steps=0, mode=1):
+def _scan_both(rk, ctx, O, ev_list, windows, n_steps, prec, lam=64.0, block_steps=0, mode=1, turn_stop=0):
     off, wid, dr = synth.pack_events(ev_list)
     ctx.upload_hits(off, wid, dr)
     total = int(sum(int(np.prod(w["count"].astype(np.int64))) for w in windows))
-    p = rk.make_scan_params(n_steps=n_steps, precision=prec, lambda_mm2=lam, block_steps=block_steps)
+    p = rk.make_scan_params(n_steps=n_steps, precision=prec, lambda_mm2=lam, block_steps=block_steps,
+                            turn_stop=turn_stop)
     score = np.zeros(total); nin = np.zeros(total, np.int32)
     bi = np.zeros(len(ev_list), np.int64); bs = np.zeros(len(ev_list))
     rk.rkn_scan_windows(ctx.ctx, p, windows, score, nin, bi, bs)
-    osc, onin, obi, obs, _ = O.scan_windows(O.params(n_steps=n_steps, lambda_mm2=lam), off, wid, dr,
-                                            windows, mode=mode)
+    osc, onin, obi, obs, _ = O.scan_windows(O.params(n_steps=n_steps, lambda_mm2=lam, turn_stop=turn_stop),
+                                            off, wid, dr, windows, mode=mode)
     return score, nin, bi, bs, osc, onin, obi, obs
 
 
@@ -95,6 +96,21 @@ def test_scan_single_turn_fp64(rk, ctx_u, orc_u, ev1):
     _note("scan single-turn FP64 6^5")
     w = synth.make_windows([(0, 0, ev1.truth_seeds[0], [0.3, 100, 10, 10, 10], [6] * 5)])
     score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_u, orc_u, [ev1], w, 2000, 64)
+    rel = pu.check_scores(score, osc, rel=1e-9, abs_=1e-9)
+    _note(f"  max rel score error {rel:.2e}")
+    assert np.array_equal(nin, onin)
+    pu.check_best(bi[0], osc)
+    assert bs[0] == pytest.approx(osc.min(), rel=1e-9)
+
+
+@pytest.mark.parametrize("turn_stop", [0, 1])
+def test_scan_solenoid_fp64(rk, ctx_s, orc_s, geo, sfield, turn_stop):
+    """FP64 scan in the (r, z) field map: one event, 6^5 = 7776 seeds over theta+-0.3,
+    z+-100, p+-10, 2000 steps, with and without the end of the turn partition."""
+    _note(f"scan solenoid FP64 6^5 turn_stop={turn_stop}")
+    ev = synth.event_single_turn(geo, sfield, 2)
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], [0.3, 100, 10, 10, 10], [6] * 5)])
+    score, nin, bi, bs, osc, onin, obi, obs = _scan_both(rk, ctx_s, orc_s, [ev], w, 2000, 64, turn_stop=turn_stop)
     rel = pu.check_scores(score, osc, rel=1e-9, abs_=1e-9)
     _note(f"  max rel score error {rel:.2e}")
     assert np.array_equal(nin, onin)
@@ -400,3 +416,38 @@ def test_hit_order_invariance(rk, geo, sfield):
     assert np.array_equal(res[1][1], res[0][1])
     assert np.array_equal(res[1][2][:, :perm.size], res[0][2][:, perm])
     _note("hit order: scores, n_in and masks follow the permutation")
+
+
+# ---------------------------------------------------------------------------------------
+# work counters of the kernel against the CPU model of its culling rule
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("fieldname", ["u", "s"])
+def test_work_counts_match_cull_model(rk, geo, ufield, sfield, ctx_u, ctx_s, fieldname):
+    """The counting instance of the scan kernel takes every step and evaluates the chord
+    distances of exactly the (block, hit) pairs the cull rule keeps (tests/cull_model.py,
+    FP64): the counts agree up to pairs whose sphere or band test sits within FP32
+    rounding of its bound."""
+    import oracle
+    from tests.cull_model import blocked_work
+    field = ufield if fieldname == "u" else sfield
+    ctx = ctx_u if fieldname == "u" else ctx_s
+    ev = synth.event_multi_turn(geo, field, 7, sigma=0.2, noise_frac=0.3)
+    off, wid, dr = synth.pack_events([ev])
+    ctx.upload_hits(off, wid, dr)
+    n_steps = 3000
+    w = synth.make_windows([(0, 0, ev.truth_seeds[0], [0.02, 20.0, 3.0, 3.0, 3.0], [2, 2, 2, 2, 2])])
+    p = rk.make_scan_params(n_steps=n_steps, precision=32)
+    B, _ = rk.rkn_scan_shape(ctx.ctx, p)
+    steps, tests, chords = rk.rkn_scan_work_counts(ctx.ctx, p, w)
+    O = oracle.Oracle(geo, field)
+    prm = O.params(n_steps=n_steps)
+    m_steps = m_chords = 0
+    for k in range(32):
+        s, c, _ = blocked_work(O, prm, O.window_seed(w[0], k), geo, ev.wire_id, ev.drift, B)
+        m_steps += s
+        m_chords += c
+    _note(f"{fieldname}: B={B} steps {steps} tests {tests} chords {chords} (model {m_chords}), "
+          f"chords/seed-step {chords / steps:.4f}")
+    assert steps == m_steps == 32 * n_steps
+    assert abs(chords - m_chords) <= 0.005 * m_chords + 2 * B
+    assert tests >= chords // B > 0

@@ -136,3 +136,42 @@ def test_hough_windows_cover_truth(geo, ufield, orc_u):
     j = int(np.argmin(dth))
     assert dth[j] < 0.06
     assert abs(ws[j]["center"][2] - t[2]) < 6 and abs(ws[j]["center"][3] - t[3]) < 6
+
+
+def _window_fields(w):
+    return (int(w.event), int(w.candidate), tuple(w.center), tuple(w.half_width), tuple(w.count))
+
+
+def test_hough_seed_windows_is_the_per_event_composition(geo, ufield, orc_u):
+    """orc_hough_seed_windows over several events equals, event by event, the
+    accumulator, the peaks in their order and the window of each peak (peaks whose
+    circle misses r = R0 skipped, candidates numbered per event), bit for bit; a short
+    output returns minus the required count."""
+    import ctypes
+    import oracle
+    evs = [synth.event_fixed_total(geo, ufield, s, n_total=120, noise_frac=0.3) for s in (0, 1, 2, 3)]
+    off, wid, dr = synth.pack_events(evs)
+    hp = orc_u.hough_params(max_cand=6, min_votes=4)
+    out = (oracle.OrcWindow * 64)()
+    n = oracle.lib().orc_hough_seed_windows(ctypes.byref(orc_u.geo), ctypes.byref(hp), len(evs),
+                                            off.ctypes.data, wid.ctypes.data, 64, out)
+    assert n > len(evs)
+    expect = []
+    for e, ev in enumerate(evs):
+        acc = orc_u.hough_accumulate(hp, ev.wire_id)
+        flats, _ = orc_u.hough_peaks(hp, acc, hp.max_cand)
+        cand = 0
+        for f in flats:
+            ow = oracle.OrcWindow()
+            if not oracle.lib().orc_hough_window(ctypes.byref(hp), acc.ctypes.data, int(f), ctypes.byref(ow)):
+                continue
+            ow.event = e
+            ow.candidate = cand
+            cand += 1
+            expect.append(_window_fields(ow))
+    assert [_window_fields(out[i]) for i in range(n)] == expect
+    short = (oracle.OrcWindow * 64)()
+    m = oracle.lib().orc_hough_seed_windows(ctypes.byref(orc_u.geo), ctypes.byref(hp), len(evs),
+                                            off.ctypes.data, wid.ctypes.data, n - 1, short)
+    assert m == -n
+    assert [_window_fields(short[i]) for i in range(n - 1)] == expect[:n - 1]

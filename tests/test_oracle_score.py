@@ -237,22 +237,26 @@ def test_band_pruning_bit_identical(geo, ufield, sfield, cfg):
         assert pp < pb
 
 
-@pytest.mark.parametrize("block", [4, 8])
-def test_block_pruning_bit_identical(geo, ufield, sfield, block):
-    """The kernel's two-level block pruning gives bit-identical E and n_in, with far fewer pairs."""
+@pytest.mark.parametrize("block", [4, 6, 8])
+def test_block_rule_bit_identical(geo, ufield, sfield, block):
+    """The scan kernel's block culling (modelled on the CPU in tests/cull_model.py, not
+    part of the oracle) keeps every pair that matters: Eq. 1 over the kept pairs' chord
+    minima equals brute force bit for bit, with far fewer chord distances."""
     import oracle
+    from tests.cull_model import blocked_work
     for f, ev in ((ufield, synth.event_multi_turn(geo, ufield, 5)),
                   (sfield, synth.event_fixed_total(geo, sfield, 1))):
         O = oracle.Oracle(geo, f)
         prm = O.params(n_steps=2999)
         rng = np.random.default_rng(12)
-        seeds = synth.random_seeds(rng, ev.truth_seeds[0], [0.2, 60, 8, 8, 8], 10)
+        seeds = synth.random_seeds(rng, ev.truth_seeds[0], [0.2, 60, 8, 8, 8], 6)
         seeds[0] = ev.truth_seeds[0]
         for s in seeds:
             Eb, nb, pb = O.score(prm, s, ev.wire_id, ev.drift, mode=0)
-            Ek, nk, cull, pk = O.score_blocked(prm, s, ev.wire_id, ev.drift, block=block)
-            assert Eb == Ek and nb == nk
-            assert pk < pb / 5 and cull < pb
+            steps, chords, Ek = blocked_work(O, prm, s, geo, ev.wire_id, ev.drift, block, want_score=True)
+            assert steps == prm.n_steps
+            assert Eb == Ek
+            assert chords < pb / 5
 
 
 # ---------------------------------------------------------------------------------------
@@ -343,3 +347,37 @@ def test_scan_windows_ties_lowest_index(geo, orc_u):
     prm = orc_u.params(n_steps=300)
     score, n_in, bi, bs, _ = orc_u.scan_windows(prm, np.array([0, 3], np.int32), ev.wire_id, ev.drift, w)
     assert np.all(score == 3 * 64.0) and bi[0] == 0
+
+
+def test_scan_seeds_matches_per_seed_score_and_window_scan(geo, ufield, orc_u):
+    """orc_scan_seeds over seeds of several events given in a scrambled order: every score
+    and n_in equals the per-seed definition (orc_score on that seed's own event) bit for
+    bit, equals the window scan of the same seeds, and each event's best is the lowest
+    score with ties to the lowest list index."""
+    evs = [synth.event_single_turn(geo, ufield, s) for s in (11, 12, 13)]
+    off, wid, dr = synth.pack_events(evs)
+    prm = orc_u.params(n_steps=900)
+    rows = []
+    for e, ev in enumerate(evs):
+        rows.append((e, 0, ev.truth_seeds[0], [0.02, 6.0, 1.5, 1.5, 1.5], [2, 2, 2, 2, 2]))
+        # a window far from the track: many seeds on the plateau E = N lambda (ties)
+        far = ev.truth_seeds[0] + np.array([1.5, 0.0, 0.0, 0.0, 0.0])
+        rows.append((e, 1, far, [0.05, 10.0, 2.0, 2.0, 2.0], [2, 1, 2, 1, 2]))
+    w = synth.make_windows(rows)
+    ws, wn, wbi, wbs, _ = orc_u.scan_windows(prm, off, wid, dr, w, mode=1)
+    sizes = [int(np.prod(x["count"])) for x in w]
+    seeds = np.concatenate([[orc_u.window_seed(x, k) for k in range(n)] for x, n in zip(w, sizes)])
+    sev = np.concatenate([np.full(n, x["event"], np.int32) for x, n in zip(w, sizes)])
+    perm = np.random.default_rng(5).permutation(seeds.shape[0])
+    sc, nin, bi, bs = orc_u.scan_seeds(prm, off, wid, dr, sev[perm], seeds[perm], mode=1)
+    assert np.array_equal(sc, ws[perm]) and np.array_equal(nin, wn[perm])
+    for j in range(0, perm.size, 7):
+        e = int(sev[perm[j]])
+        E, n_in, _ = orc_u.score(prm, seeds[perm[j]], evs[e].wire_id, evs[e].drift, mode=0)
+        assert E == sc[j] and n_in == nin[j]
+    for e in range(len(evs)):
+        mine = np.nonzero(sev[perm] == e)[0]
+        best = mine[np.argmin(sc[mine])]          # argmin: first (lowest list index) on ties
+        assert bi[e] == best and bs[e] == sc[best] == wbs[e]
+        assert ws[wbi[e]] == wbs[e]
+    assert np.any(sc == sc.max()) and np.sum(sc == sc.max()) > 1   # the plateau has ties

@@ -69,8 +69,10 @@ def test_turn_end_against_closed_form_helix(orc_uni):
 
 @pytest.mark.parametrize("kind", ["uniform", "solenoid"])
 def test_turn_stop_scores_agree(geo, ufield, sfield, kind):
-    """Brute force, band-pruned and block-pruned scores are identical under the stop
-    rule, and equal the score of the same track cut to its own step count."""
+    """Brute force, band-pruned and block-culled scores (the kernel's rule, modelled in
+    tests/cull_model.py) are identical under the stop rule, and equal the score of the
+    same track cut to its own step count."""
+    from tests.cull_model import blocked_work
     field = ufield if kind == "uniform" else sfield
     O = oracle.Oracle(geo, field)
     ev = synth.event_multi_turn(geo, field, 1)
@@ -81,8 +83,8 @@ def test_turn_stop_scores_agree(geo, ufield, sfield, kind):
         E0, n0, _ = O.score(stop, s, ev.wire_id, ev.drift, mode=0)
         E1, n1, _ = O.score(stop, s, ev.wire_id, ev.drift, mode=1)
         for B in (4, 6, 8):
-            Eb, nb, _, _ = O.score_blocked(stop, s, ev.wire_id, ev.drift, B)
-            assert Eb == E0 and nb == n0
+            _, _, Eb = blocked_work(O, stop, s, geo, ev.wire_id, ev.drift, B, want_score=True)
+            assert Eb == E0
         assert E1 == E0 and n1 == n0
         # the step count of the turn: the first state inside r < R0
         tr = O.trace(O.params(n_steps=6000), s, np.arange(6001))[0]
