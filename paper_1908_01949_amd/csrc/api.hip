@@ -229,11 +229,15 @@ rkn_status rkn_upload_field_rz(rkn_ctx* c, int32_t nr, int32_t nz, double r0, do
   if (!is_fin(r0) || !is_fin(r1) || !is_fin(z0) || !is_fin(z1) || r1 <= r0 || z1 <= z0 || r0 < 0)
     return arg_err(c, "bad field grid extent");
   if (!br || !bz) return arg_err(c, "NULL field array");
-  std::vector<float2> nodes((size_t)nr * nz);
-  for (size_t i = 0; i < nodes.size(); ++i) {
+  for (size_t i = 0; i < (size_t)nr * nz; ++i)
     if (!std::isfinite(br[i]) || !std::isfinite(bz[i])) return arg_err(c, "non-finite field node");
-    nodes[i] = make_float2(br[i], bz[i]);
-  }
+  // device layout: [nz + 1][nr + 1], the extra column and row repeating the edge
+  std::vector<float2> nodes(rkn::padded_field_nodes(nr, nz));
+  for (int j = 0; j <= nz; ++j)
+    for (int i = 0; i <= nr; ++i) {
+      const size_t src = (size_t)std::min(j, nz - 1) * nr + std::min(i, nr - 1);
+      nodes[(size_t)j * (nr + 1) + i] = make_float2(br[src], bz[src]);
+    }
   RKN_HIP(hipSetDevice(c->device), "hipSetDevice");
   RKN_HIP(upload(c->field_nodes, nodes.data(), nodes.size(), c->stream), "field upload");
   RKN_HIP(hipStreamSynchronize(c->stream), "field upload");

@@ -18,13 +18,20 @@ struct alignas(sizeof(R) * 8) HitRec {
   R mx, my, mz, ux, uy, uz, L, drift;
 };
 
-// Axisymmetric field: uniform B_z, or FP32 (B_r, B_z) nodes interleaved [nz][nr].
+// Axisymmetric field: uniform B_z, or FP32 (B_r, B_z) nodes interleaved
+// [nz + 1][stride = nr + 1]: the extra column and row repeat the edge nodes, so a
+// coordinate clamped to the upper edge selects a cell whose far nodes carry weight 0
+// and no index clamp is needed.
 struct FieldDev {
   const float2* nodes;
   int nr, nz;
+  int stride;
   double r0, z0, inv_dr, inv_dz;
   double bz;
 };
+
+// Nodes of the padded table (the layout FieldDev describes).
+__host__ __device__ inline size_t padded_field_nodes(int nr, int nz) { return (size_t)(nr + 1) * (nz + 1); }
 
 template <typename R>
 __device__ __forceinline__ R clampv(R v, R lo, R hi) {
@@ -51,39 +58,43 @@ __device__ __forceinline__ R frcp(R x) {
   }
 }
 
-// Bilinear (r, z) interpolation clamped to the grid edge; B_x,y = B_r (x, y)/r.
-// `nodes` is the map in LDS (staged by the caller) or in global memory. The cell
-// index is truncated from the clamped coordinate, which equals the floor there.
+// Bilinear (r, z) interpolation clamped to the grid edge, scaled by sc:
+// (bx, by, bz) = sc B with B_x,y = B_r (x, y)/r. `nodes` is the padded map in LDS
+// (staged by the caller) or in global memory; r2 = x^2 + y^2 is passed in.
 template <typename R>
-__device__ __forceinline__ void field_rz(const FieldDev& f, const float2* nodes, R x, R y, R z, R& bx, R& by,
-                                         R& bz) {
+__device__ __forceinline__ void field_rz_r2(const FieldDev& f, const float2* nodes, R x, R y, R z, R r2, R sc,
+                                            R& bx, R& by, R& bz) {
   if constexpr (sizeof(R) == 4) {
-    // FP32: one rsq, clamps by med3, the cell from floor in float (exact for the
-    // small integers involved), and the node index from one fma.
-    const float r2 = fmaf(x, x, y * y);
-    const float inv_r = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+    // FP32: one rsq, clamps by med3; the clamped coordinate is >= 0, so truncation
+    // is the floor and fract the cell offset; at the upper edge the cell is the
+    // padding one (offset 0)
+    // + 1e-30 keeps rsq finite on the axis (r = 0 there) and vanishes against any
+    // r^2 above 1e-22 mm^2
+    const float inv_r = __builtin_amdgcn_rsqf(r2 + 1e-30f);
     const float r = r2 * inv_r;
-    const float fnr = (float)f.nr, fnz = (float)f.nz;
-    const float u = __builtin_amdgcn_fmed3f(fmaf(r, (float)f.inv_dr, (float)(-f.r0 * f.inv_dr)), 0.0f, fnr - 1.0f);
-    const float v = __builtin_amdgcn_fmed3f(fmaf(z, (float)f.inv_dz, (float)(-f.z0 * f.inv_dz)), 0.0f, fnz - 1.0f);
-    const float fi = fminf(floorf(u), fnr - 2.0f);
-    const float fj = fminf(floorf(v), fnz - 2.0f);
-    const float a = u - fi, b = v - fj;
-    const float2* row0 = nodes + (int)fmaf(fj, fnr, fi);
-    const float2* row1 = row0 + f.nr;
+    const float u = __builtin_amdgcn_fmed3f(fmaf(r, (float)f.inv_dr, (float)(-f.r0 * f.inv_dr)), 0.0f,
+                                            (float)(f.nr - 1));
+    const float v = __builtin_amdgcn_fmed3f(fmaf(z, (float)f.inv_dz, (float)(-f.z0 * f.inv_dz)), 0.0f,
+                                            (float)(f.nz - 1));
+    const float a = __builtin_amdgcn_fractf(u), b = __builtin_amdgcn_fractf(v);
+    unsigned idx = __umul24((unsigned)(int)v, (unsigned)f.stride) + (unsigned)(int)u;
+    // keep the node index as one value (one multiply-add, then one shift-add into the
+    // address) rather than two shifted terms
+    asm volatile("" : "+v"(idx));
+    const float2* row0 = nodes + idx;
+    const float2* row1 = row0 + f.stride;
     const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
     const float br0 = fmaf(a, n01.x - n00.x, n00.x);
     const float br1 = fmaf(a, n11.x - n10.x, n10.x);
     const float bz0 = fmaf(a, n01.y - n00.y, n00.y);
     const float bz1 = fmaf(a, n11.y - n10.y, n10.y);
     const float br = fmaf(b, br1 - br0, br0);
-    bz = fmaf(b, bz1 - bz0, bz0);
+    bz = sc * fmaf(b, bz1 - bz0, bz0);
     // on the axis x = y = 0, so B_x = B_y = 0 whatever inv_r is (finite here)
-    const float s = br * inv_r;
+    const float s = br * (sc * inv_r);
     bx = s * x;
     by = s * y;
   } else {
-    const R r2 = x * x + y * y;
     const R r = sqrt(r2);
     const R inv_r = r > (R)1e-9 ? (R)1 / r : (R)0;
     const R u = clampv((r - (R)f.r0) * (R)f.inv_dr, (R)0, (R)(f.nr - 1));
@@ -93,19 +104,52 @@ __device__ __forceinline__ void field_rz(const FieldDev& f, const float2* nodes,
     const int j = jv < f.nz - 2 ? jv : f.nz - 2;
     const R a = u - (R)i;
     const R b = v - (R)j;
-    const float2* row0 = nodes + j * f.nr + i;
-    const float2* row1 = row0 + f.nr;
+    const float2* row0 = nodes + j * f.stride + i;
+    const float2* row1 = row0 + f.stride;
     const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
     const R br0 = (R)n00.x + a * ((R)n01.x - (R)n00.x);
     const R br1 = (R)n10.x + a * ((R)n11.x - (R)n10.x);
     const R bz0 = (R)n00.y + a * ((R)n01.y - (R)n00.y);
     const R bz1 = (R)n10.y + a * ((R)n11.y - (R)n10.y);
     const R br = br0 + b * (br1 - br0);
-    bz = bz0 + b * (bz1 - bz0);
-    const R s = br * inv_r;
+    bz = sc * (bz0 + b * (bz1 - bz0));
+    const R s = sc * (br * inv_r);
     bx = s * x;
     by = s * y;
   }
+}
+
+template <typename R>
+__device__ __forceinline__ R vmin(R a, R b) {
+  if constexpr (sizeof(R) == 4) {
+    return fminf(a, b);
+  } else {
+    return fmin(a, b);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R vmax(R a, R b) {
+  if constexpr (sizeof(R) == 4) {
+    return fmaxf(a, b);
+  } else {
+    return fmax(a, b);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R radius2(R x, R y) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_fmaf(x, x, y * y);
+  } else {
+    return __builtin_fma(x, x, y * y);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void field_rz(const FieldDev& f, const float2* nodes, R x, R y, R z, R& bx, R& by,
+                                         R& bz) {
+  field_rz_r2<R>(f, nodes, x, y, z, radius2(x, y), (R)1, bx, by, bz);
 }
 
 // Whether (x, y) lies strictly inside the seed cylinder r < R0 (r0sq = R0^2 in the
@@ -114,11 +158,7 @@ __device__ __forceinline__ void field_rz(const FieldDev& f, const float2* nodes,
 // same state.
 template <typename R>
 __device__ __forceinline__ bool inside_r0(R x, R y, R r0sq) {
-  if constexpr (sizeof(R) == 4) {
-    return __builtin_fmaf(x, x, y * y) < r0sq;
-  } else {
-    return __builtin_fma(x, x, y * y) < r0sq;
-  }
+  return radius2(x, y) < r0sq;
 }
 
 // Propagation state. For FP32 the position and the direction carry Kahan
@@ -162,61 +202,153 @@ __device__ __forceinline__ void advance(State<R>& st, R dx, R dy, R dz) {
 }
 
 // One RKN4 step (Nystrom formula for x'' = lam x' x B(x), three field evaluations:
-// start, middle, end). FIELD 0: uniform B_z; FIELD 1: (r, z) map.
+// start, middle, end) as increments: from the position p and unit direction t, the
+// changes d[0..2] of the position and d[3..5] of the direction over a step h.
+// FIELD 0: uniform B_z; FIELD 1: (r, z) map, where the field is evaluated already
+// scaled by lam (k = t x (lam B)) and r2 = px^2 + py^2 comes from the caller.
 template <typename R, int FIELD>
-__device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, const float2* nodes, R h) {
+__device__ __forceinline__ void rkn_delta(const FieldDev& f, const float2* nodes, R lam, R h, R px, R py, R pz,
+                                          R tx, R ty, R tz, R r2, R d[6]) {
   const R h2 = (R)0.5 * h, hh6 = h * h / (R)6, h6 = h / (R)6;
   if constexpr (FIELD == 0) {
-    const R a = st.lam * (R)f.bz;
-    const R k1x = a * st.ty, k1y = -a * st.tx;
-    const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y;
+    const R a = lam * (R)f.bz;
+    const R k1x = a * ty, k1y = -a * tx;
+    const R t2x = tx + h2 * k1x, t2y = ty + h2 * k1y;
     const R k2x = a * t2y, k2y = -a * t2x;
-    const R t3x = st.tx + h2 * k2x, t3y = st.ty + h2 * k2y;
+    const R t3x = tx + h2 * k2x, t3y = ty + h2 * k2y;
     const R k3x = a * t3y, k3y = -a * t3x;
-    const R t4x = st.tx + h * k3x, t4y = st.ty + h * k3y;
+    const R t4x = tx + h * k3x, t4y = ty + h * k3y;
     const R k4x = a * t4y, k4y = -a * t4x;
-    const R dx = h * st.tx + hh6 * (k1x + k2x + k3x);
-    const R dy = h * st.ty + hh6 * (k1y + k2y + k3y);
-    const R dz = h * st.tz;
-    turn(st.tx, st.ctx, h6 * (k1x + (R)2 * (k2x + k3x) + k4x));
-    turn(st.ty, st.cty, h6 * (k1y + (R)2 * (k2y + k3y) + k4y));
-    advance(st, dx, dy, dz);
+    d[0] = h * tx + hh6 * (k1x + k2x + k3x);
+    d[1] = h * ty + hh6 * (k1y + k2y + k3y);
+    d[2] = h * tz;
+    d[3] = h6 * (k1x + (R)2 * (k2x + k3x) + k4x);
+    d[4] = h6 * (k1y + (R)2 * (k2y + k3y) + k4y);
+    d[5] = (R)0;
   } else {
-    const R l = st.lam;
-    R bx, by, bz;
-    field_rz(f, nodes, st.x, st.y, st.z, bx, by, bz);
-    const R k1x = l * (st.ty * bz - st.tz * by);
-    const R k1y = l * (st.tz * bx - st.tx * bz);
-    const R k1z = l * (st.tx * by - st.ty * bx);
+    R bx, by, bz;   // lam B
+    field_rz_r2(f, nodes, px, py, pz, r2, lam, bx, by, bz);
+    const R k1x = ty * bz - tz * by;
+    const R k1y = tz * bx - tx * bz;
+    const R k1z = tx * by - ty * bx;
     const R hh8 = h * h * (R)0.125;
-    field_rz(f, nodes, st.x + h2 * st.tx + hh8 * k1x, st.y + h2 * st.ty + hh8 * k1y,
-             st.z + h2 * st.tz + hh8 * k1z, bx, by, bz);
-    const R t2x = st.tx + h2 * k1x, t2y = st.ty + h2 * k1y, t2z = st.tz + h2 * k1z;
-    // stages 2 and 3 share the middle field: scale it by Lambda once
-    const R lbx = l * bx, lby = l * by, lbz = l * bz;
-    const R k2x = t2y * lbz - t2z * lby;
-    const R k2y = t2z * lbx - t2x * lbz;
-    const R k2z = t2x * lby - t2y * lbx;
-    const R t3x = st.tx + h2 * k2x, t3y = st.ty + h2 * k2y, t3z = st.tz + h2 * k2z;
-    const R k3x = t3y * lbz - t3z * lby;
-    const R k3y = t3z * lbx - t3x * lbz;
-    const R k3z = t3x * lby - t3y * lbx;
+    {
+      const R qx = px + h2 * tx + hh8 * k1x, qy = py + h2 * ty + hh8 * k1y;
+      field_rz_r2(f, nodes, qx, qy, pz + h2 * tz + hh8 * k1z, radius2(qx, qy), lam, bx, by, bz);
+    }
+    // stages 2 and 3 share the middle field
+    const R t2x = tx + h2 * k1x, t2y = ty + h2 * k1y, t2z = tz + h2 * k1z;
+    const R k2x = t2y * bz - t2z * by;
+    const R k2y = t2z * bx - t2x * bz;
+    const R k2z = t2x * by - t2y * bx;
+    const R t3x = tx + h2 * k2x, t3y = ty + h2 * k2y, t3z = tz + h2 * k2z;
+    const R k3x = t3y * bz - t3z * by;
+    const R k3y = t3z * bx - t3x * bz;
+    const R k3z = t3x * by - t3y * bx;
     const R hh2 = h * h * (R)0.5;
-    field_rz(f, nodes, st.x + h * st.tx + hh2 * k3x, st.y + h * st.ty + hh2 * k3y,
-             st.z + h * st.tz + hh2 * k3z, bx, by, bz);
-    const R t4x = st.tx + h * k3x, t4y = st.ty + h * k3y, t4z = st.tz + h * k3z;
-    const R k4x = l * (t4y * bz - t4z * by);
-    const R k4y = l * (t4z * bx - t4x * bz);
-    const R k4z = l * (t4x * by - t4y * bx);
-    const R dx = h * st.tx + hh6 * (k1x + k2x + k3x);
-    const R dy = h * st.ty + hh6 * (k1y + k2y + k3y);
-    const R dz = h * st.tz + hh6 * (k1z + k2z + k3z);
-    turn(st.tx, st.ctx, h6 * (k1x + (R)2 * (k2x + k3x) + k4x));
-    turn(st.ty, st.cty, h6 * (k1y + (R)2 * (k2y + k3y) + k4y));
-    turn(st.tz, st.ctz, h6 * (k1z + (R)2 * (k2z + k3z) + k4z));
-    advance(st, dx, dy, dz);
+    {
+      const R qx = px + h * tx + hh2 * k3x, qy = py + h * ty + hh2 * k3y;
+      field_rz_r2(f, nodes, qx, qy, pz + h * tz + hh2 * k3z, radius2(qx, qy), lam, bx, by, bz);
+    }
+    const R t4x = tx + h * k3x, t4y = ty + h * k3y, t4z = tz + h * k3z;
+    const R k4x = t4y * bz - t4z * by;
+    const R k4y = t4z * bx - t4x * bz;
+    const R k4z = t4x * by - t4y * bx;
+    d[0] = h * tx + hh6 * (k1x + k2x + k3x);
+    d[1] = h * ty + hh6 * (k1y + k2y + k3y);
+    d[2] = h * tz + hh6 * (k1z + k2z + k3z);
+    d[3] = h6 * (k1x + (R)2 * (k2x + k3x) + k4x);
+    d[4] = h6 * (k1y + (R)2 * (k2y + k3y) + k4y);
+    d[5] = h6 * (k1z + (R)2 * (k2z + k3z) + k4z);
   }
 }
+
+// One step applied to a State: FP32 with Kahan-compensated position and direction
+// at every step (the adaptive path, whose trial steps can be rejected), FP64 plain.
+template <typename R, int FIELD>
+__device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, const float2* nodes, R h) {
+  R d[6];
+  rkn_delta<R, FIELD>(f, nodes, st.lam, h, st.x, st.y, st.z, st.tx, st.ty, st.tz,
+                      FIELD == 1 ? radius2(st.x, st.y) : (R)0, d);
+  turn(st.tx, st.ctx, d[3]);
+  turn(st.ty, st.cty, d[4]);
+  if (FIELD == 1) turn(st.tz, st.ctz, d[5]);
+  advance(st, d[0], d[1], d[2]);
+}
+
+// Fixed-step propagation with block-relative sums. The State holds the origin of the
+// current block (position and direction with their Kahan compensation terms); the
+// current position p and direction t are that origin plus the plain sum q, u of the
+// increments since the block started. fold() adds q and u into the origin with
+// compensation and starts a new block at the result. In FP32 this keeps the origin's
+// compensation (the sums of ~1 mm increments into ~800 mm positions, and of ~3e-3
+// increments into unit directions, would otherwise drift by up to ~0.2 mm over 6000
+// steps) while each step makes only plain adds; callers fold at the same step
+// indices (the ends of the scan's cull blocks), so every kernel that recomputes a
+// trajectory reproduces it exactly. In FP64 every step is a plain add into p and t
+// (the oracle's sums) and fold() stores them.
+template <typename R, int FIELD>
+struct Prop {
+  R px, py, pz, tx, ty, tz;   // current position and direction
+  R qx, qy, qz, ux, uy, uz;   // increments since the block started (FP32)
+  R r2;                       // px^2 + py^2
+  __device__ __forceinline__ void start(const State<R>& s) {
+    px = s.x;
+    py = s.y;
+    pz = s.z;
+    tx = s.tx;
+    ty = s.ty;
+    tz = s.tz;
+    qx = qy = qz = ux = uy = uz = (R)0;
+    r2 = radius2(px, py);
+  }
+  __device__ __forceinline__ void step(const State<R>& s, const FieldDev& f, const float2* nodes, R h) {
+    R d[6];
+    rkn_delta<R, FIELD>(f, nodes, s.lam, h, px, py, pz, tx, ty, tz, r2, d);
+    if constexpr (sizeof(R) == 4) {
+      qx += d[0];
+      qy += d[1];
+      qz += d[2];
+      ux += d[3];
+      uy += d[4];
+      px = s.x + qx;
+      py = s.y + qy;
+      pz = s.z + qz;
+      tx = s.tx + ux;
+      ty = s.ty + uy;
+      if constexpr (FIELD == 1) {
+        uz += d[5];
+        tz = s.tz + uz;
+      }
+    } else {
+      px += d[0];
+      py += d[1];
+      pz += d[2];
+      tx += d[3];
+      ty += d[4];
+      if constexpr (FIELD == 1) tz += d[5];
+    }
+    r2 = radius2(px, py);
+  }
+  __device__ __forceinline__ void fold(State<R>& s) {
+    if constexpr (sizeof(R) == 4) {
+      kahan_add(s.x, s.cx, qx);
+      kahan_add(s.y, s.cy, qy);
+      kahan_add(s.z, s.cz, qz);
+      kahan_add(s.tx, s.ctx, ux);
+      kahan_add(s.ty, s.cty, uy);
+      if constexpr (FIELD == 1) kahan_add(s.tz, s.ctz, uz);
+    } else {
+      s.x = px;
+      s.y = py;
+      s.z = pz;
+      s.tx = tx;
+      s.ty = ty;
+      s.tz = tz;
+    }
+    start(s);
+  }
+};
 
 // The same step with the local error estimate of the adaptive step size: err =
 // h^2 |k1 - k2 - k3 + k4| (the stage accelerations agree to O(h^2) for a smooth

@@ -78,6 +78,9 @@ __device__ __forceinline__ void window_seed(const WindowDev& W, int64_t k, doubl
 }
 
 constexpr int kMaxCand = 64;     // Hough candidates kept per event, upper bound
+// Steps per block of the refinement's forward pass; its adjoint recompute folds the
+// block-relative sums at the same steps.
+constexpr int kRefineBlock = 8;
 
 struct HoughDev {
   int n_xy, n_r;

@@ -43,8 +43,8 @@ __device__ __forceinline__ void field_rz_jac(const FieldDev& f, float x, float y
   const int i = iu < f.nr - 2 ? iu : f.nr - 2;
   const int j = jv < f.nz - 2 ? jv : f.nz - 2;
   const float a = u - (float)i, b = v - (float)j;
-  const float2* row0 = f.nodes + j * f.nr + i;
-  const float2* row1 = row0 + f.nr;
+  const float2* row0 = f.nodes + j * f.stride + i;
+  const float2* row1 = row0 + f.stride;
   const float2 n00 = row0[0], n01 = row0[1], n10 = row1[0], n11 = row1[1];
   const float r0r = n00.x + a * (n01.x - n00.x), r1r = n10.x + a * (n11.x - n10.x);
   const float r0z = n00.y + a * (n01.y - n00.y), r1z = n10.y + a * (n11.y - n10.y);
@@ -323,22 +323,42 @@ __global__ void __launch_bounds__(64) adj_seg_kernel(BwdArgs a) {
     q.lam = lam;
     return q;
   };
-  // With the turn-partition stop the forward pass took a step only while every
-  // earlier step ended outside r < R0 (the seed itself is not tested) and froze the
-  // state after that; steps from first_frozen on leave the state as it is (M = I).
+  // The forward pass's propagation: block-relative sums folded at the ends of its
+  // kRefineBlock-step blocks (and at the last step) when the track was live at the
+  // block's start; the checkpoint is taken right after a fold. With the
+  // turn-partition stop the forward pass took a step only while every earlier step
+  // ended outside r < R0 (the seed itself is not tested) and froze the state after
+  // that; steps from first_frozen on leave the state as it is (M = I).
   const float r0sq = (float)(a.R0 * a.R0);
   bool live = !(a.turn_stop && k > 0 && inside_r0(s.x, s.y, r0sq));
+  bool live_blk = live;
   int first_frozen = live ? n1 : n0;
-  put(0, s);
+  Prop<float, FIELD> pr;
+  pr.start(s);
+  auto cur = [&]() {
+    State<float> q = s;
+    q.x = pr.px;
+    q.y = pr.py;
+    q.z = pr.pz;
+    q.tx = pr.tx;
+    q.ty = pr.ty;
+    q.tz = pr.tz;
+    return q;
+  };
+  put(0, cur());
   for (int j = 1; j <= n1 - n0; ++j) {
     if (live) {
-      rkn_step<float, FIELD>(s, a.field, a.field.nodes, a.h);
-      if (a.turn_stop && inside_r0(s.x, s.y, r0sq)) {
+      pr.step(s, a.field, a.field.nodes, a.h);
+      if (a.turn_stop && inside_r0(pr.px, pr.py, r0sq)) {
         live = false;
         first_frozen = n0 + j;
       }
     }
-    put(j, s);
+    if ((n0 + j) % kRefineBlock == 0 || n0 + j == a.n_steps) {
+      if (live_blk) pr.fold(s);
+      live_blk = live;
+    }
+    put(j, cur());
   }
   const int e = a.seed_event[p];
   const int hb = a.ev_off[e];

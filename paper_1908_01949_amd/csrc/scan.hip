@@ -39,8 +39,12 @@ constexpr int kCap = 192;          // work-list entries per wave
 constexpr int kTabBins = 1024;     // 1 mm radial bins, the last one open-ended
 constexpr float kBandMargin = 1.0f;   // radial band table
 constexpr float kCullMargin = 0.05f;  // sphere test: covers FP32 rounding of the test (~1e-2 mm)
-constexpr int kSectors = 64;          // twisted-azimuth sectors of the candidate table
+constexpr int kSectors = 128;         // twisted-azimuth sectors of the candidate table
+// A sector entry: the run's first hit (bits 0-8) and length (bits 9-15); kSectAll
+// stands for the whole layer (a run longer than 127 hits, or a reach past pi).
+constexpr uint32_t kSectAll = 0xffffu;
 constexpr int kTouchWords = (RKN_MAX_HITS_PER_EVENT + 31) / 32;   // per-wave row bitmap
+constexpr int kTraceFold = 8;   // rkn_trace: steps between folds of the block-relative sums
 constexpr float kPi = 3.14159265358979f;
 
 struct ScanArgs {
@@ -356,7 +360,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   float2* s_field = reinterpret_cast<float2*>(smem);
   HitRec<R>* s_hits = reinterpret_cast<HitRec<R>*>(smem + a.field_bytes);
   uint16_t* s_ltab = reinterpret_cast<uint16_t*>(smem + a.field_bytes + a.hits_bytes);
-  uint32_t* s_sect = reinterpret_cast<uint32_t*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2);
+  uint16_t* s_sect = reinterpret_cast<uint16_t*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2);
   R* s_pts = reinterpret_cast<R*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2 + a.sect_bytes);
   uint32_t* s_items = reinterpret_cast<uint32_t*>(s_pts + WAVES * (B + 1) * 3 * 64);
   __shared__ int s_loff[RKN_MAX_LAYERS + 1];
@@ -390,7 +394,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   int cur_event = -1;
   const float2* nodes = nullptr;
   if constexpr (FIELD == 1) {
-    const int nn = a.field.nr * a.field.nz;
+    const int nn = (int)padded_field_nodes(a.field.nr, a.field.nz);
     for (int i = tid; i < nn; i += TILE) s_field[i] = a.field.nodes[i];
     nodes = s_field;   // made visible by the first tile's barrier
   }
@@ -433,7 +437,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       for (int q = tid; q < a.n_layers * kSectors; q += TILE) {
         const int l = q / kSectors, k = q - l * kSectors;
         const int lb = loff[l], nl = loff[l + 1] - lb;
-        uint32_t ent = 0;
+        uint32_t ent = 0u;
         if (nl > 0) {
           const float2 tw = a.layer_twist[(size_t)ev * a.n_layers + l];
           const float rl = a.layer_r[l].x - rho;
@@ -441,7 +445,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           const float dphi = ratio < 1.0f ? 2.0f * asinf(ratio) : kPi;
           const float W = dphi + fabsf(tw.x) * rho + tw.y + 2e-3f;
           if (W >= kPi) {
-            ent = (uint32_t)nl << 16;
+            ent = kSectAll;
           } else {
             const float a0 = -kPi + (2.0f * kPi / kSectors) * k, a1 = a0 + 2.0f * kPi / kSectors;
             auto inside = [&](int j) {
@@ -461,10 +465,10 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
               prev = in;
             }
             if (cnt == nl) start = 0;
-            ent = cnt > 0 ? ((uint32_t)start | ((uint32_t)cnt << 16)) : 0u;
+            ent = cnt > 127 ? kSectAll : (cnt > 0 ? ((uint32_t)start | ((uint32_t)cnt << 9)) : 0u);
           }
         }
-        s_sect[q] = ent;
+        s_sect[q] = (uint16_t)ent;
       }
       cur_event = ev;
     }
@@ -497,6 +501,8 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       st.cx = st.cy = st.cz = (R)0;
       st.ctx = st.cty = st.ctz = (R)0;
     }
+    Prop<R, FIELD> pr;   // fixed steps: current point and the block's increments
+    pr.start(st);
     if (lane < kTouchWords) touch[lane] = 0u;
     __syncthreads();
 
@@ -556,11 +562,11 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       pts[0 * 64 + lane] = st.x;
       pts[1 * 64 + lane] = st.y;
       pts[2 * 64 + lane] = st.z;
-      R r2min = st.x * st.x + st.y * st.y, r2max = r2min;
-      R cx = st.x, cy = st.y, cz = st.z;
+      R r2min, r2max;
+      if constexpr (ADAPT) {
+        r2min = r2max = radius2(st.x, st.y);
 #pragma unroll
-      for (int j = 1; j <= B; ++j) {
-        if constexpr (ADAPT) {
+        for (int j = 1; j <= B; ++j) {
           // one trial step; accepted when its error estimate is within the bound
           // (or it is the smallest step), else the lane stays and retries shorter
           if (live) {
@@ -581,22 +587,44 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
             }
             hl = hl > (R)a.h_max ? (R)a.h_max : (hl < (R)a.h_min ? (R)a.h_min : hl);
           }
-        } else {
-          if (j <= nb && (!STOP || live)) rkn_step<R, FIELD>(st, a.field, nodes, h);
+          pts[(j * 3 + 0) * 64 + lane] = st.x;
+          pts[(j * 3 + 1) * 64 + lane] = st.y;
+          pts[(j * 3 + 2) * 64 + lane] = st.z;
+          const R r2 = radius2(st.x, st.y);
+          r2min = vmin(r2min, r2);
+          r2max = vmax(r2max, r2);
         }
-        pts[(j * 3 + 0) * 64 + lane] = st.x;
-        pts[(j * 3 + 1) * 64 + lane] = st.y;
-        pts[(j * 3 + 2) * 64 + lane] = st.z;
-        const R r2 = st.x * st.x + st.y * st.y;
-        if constexpr (VAR == 1) live = live && !inside_r0(st.x, st.y, r0sq);
-        r2min = r2 < r2min ? r2 : r2min;
-        r2max = r2 > r2max ? r2 : r2max;
-        if (j == jc) {
-          cx = st.x;
-          cy = st.y;
-          cz = st.z;
+      } else {
+        r2min = r2max = pr.r2;
+        auto take = [&](int j, bool go) {
+          if (go) pr.step(st, a.field, nodes, h);
+          pts[(j * 3 + 0) * 64 + lane] = pr.px;
+          pts[(j * 3 + 1) * 64 + lane] = pr.py;
+          pts[(j * 3 + 2) * 64 + lane] = pr.pz;
+          if constexpr (VAR == 1) live = live && !inside_r0(pr.px, pr.py, r0sq);
+          r2min = vmin(r2min, pr.r2);
+          r2max = vmax(r2max, pr.r2);
+        };
+        if (nb == B) {   // every block but a short last one: straight-line steps
+#pragma unroll
+          for (int j = 1; j <= B; ++j) take(j, !STOP || live);
+        } else {
+          for (int j = 1; j <= B; ++j) take(j, j <= nb && (!STOP || live));
+        }
+        // the block's increments go into the origin; the folded position (within an
+        // ulp of the last one) ends the block's last chord and starts the next block
+        if (!STOP || live0) {
+          pr.fold(st);
+          pts[(nb * 3 + 0) * 64 + lane] = pr.px;
+          pts[(nb * 3 + 1) * 64 + lane] = pr.py;
+          pts[(nb * 3 + 2) * 64 + lane] = pr.pz;
+          r2min = vmin(r2min, pr.r2);
+          r2max = vmax(r2max, pr.r2);
         }
       }
+      // the block's middle point, from this lane's own column
+      const R cx = pts[(jc * 3 + 0) * 64 + lane], cy = pts[(jc * 3 + 1) * 64 + lane],
+              cz = pts[(jc * 3 + 2) * 64 + lane];
       // radial range of the block's chords (a chord point is within hmax/2 of an endpoint)
       const float rmin = fmaxf((float)fsqrt(r2min) - 0.5f * (float)hmax, 0.0f);
       const float rmax = (float)fsqrt(r2max);
@@ -616,9 +644,10 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         const float psic = wrap_pi(phic - s_slope[l] * (float)cz);
         int sect = (int)((psic + kPi) * (kSectors / (2.0f * kPi)));
         sect = sect < 0 ? 0 : (sect > kSectors - 1 ? kSectors - 1 : sect);
-        const uint32_t ent = has ? s_sect[l * kSectors + sect] : 0u;
-        const int start = (int)(ent & 0xffffu), cnt = (int)(ent >> 16);
+        const uint32_t ent = has ? (uint32_t)s_sect[l * kSectors + sect] : 0u;
         const int lb = s_loff[l], nl = s_loff[l + 1] - lb;
+        const bool all = ent == kSectAll;
+        const int start = all ? 0 : (int)(ent & 511u), cnt = all ? nl : (int)(ent >> 9);
         for (int k = 0; __ballot(k < cnt) != 0; ++k) {
           const bool act = k < cnt;
           int idx = start + k;
@@ -794,16 +823,16 @@ event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restr
   }
 }
 
-// LDS bytes of the layer x sector candidate table (uint32 entries, 256-byte rounded).
+// LDS bytes of the layer x sector candidate table (uint16 entries, 256-byte rounded).
 static size_t sect_table_bytes(const rkn_ctx* c) {
-  return ((size_t)std::max(c->n_layers, 1) * kSectors * 4 + 255) & ~(size_t)255;
+  return ((size_t)std::max(c->n_layers, 1) * kSectors * sizeof(uint16_t) + 255) & ~(size_t)255;
 }
 
 // LDS bytes of one workgroup of scan_kernel<R, FIELD, B, WAVES, ...>.
 static size_t scan_lds_bytes(const rkn_ctx* c, size_t rsize, int field, int B, int waves) {
   const size_t hits = ((size_t)c->max_hits_event * (rsize == 4 ? sizeof(HitRec<float>) : sizeof(HitRec<double>)) +
                        255) & ~(size_t)255;
-  const size_t fld = field == 1 ? (((size_t)c->nr * c->nz * sizeof(float2)) + 255) & ~(size_t)255 : 0;
+  const size_t fld = field == 1 ? ((padded_field_nodes(c->nr, c->nz) * sizeof(float2)) + 255) & ~(size_t)255 : 0;
   return fld + hits + kTabBins * 2 + sect_table_bytes(c) + (size_t)waves * (B + 1) * 3 * 64 * rsize +
          (size_t)waves * kCap * 4;
 }
@@ -861,7 +890,7 @@ template <typename R, int FIELD, int B, int WAVES, int MODE = 0>
 static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only, DevBuf& slab_buf) {
   constexpr int TILE = 64 * WAVES;
   const int hits_bytes = ((c->max_hits_event * (int)sizeof(HitRec<R>)) + 255) & ~255;
-  const int field_bytes = FIELD == 1 ? ((c->nr * c->nz * (int)sizeof(float2)) + 255) & ~255 : 0;
+  const int field_bytes = FIELD == 1 ? (((int)padded_field_nodes(c->nr, c->nz) * (int)sizeof(float2)) + 255) & ~255 : 0;
   a.hits_bytes = hits_bytes;
   a.field_bytes = field_bytes;
   a.sect_bytes = (int)sect_table_bytes(c);
@@ -921,6 +950,7 @@ FieldDev field_dev(const rkn_ctx* c) {
     f.nodes = c->field_nodes.as<float2>();
     f.nr = c->nr;
     f.nz = c->nz;
+    f.stride = c->nr + 1;
     f.r0 = c->r0;
     f.z0 = c->z0;
     f.inv_dr = (double)(c->nr - 1) / (c->r1 - c->r0);
@@ -971,6 +1001,7 @@ hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_til
   a.n_pos = n_pos;
   a.max_hits = c->max_hits_event > 0 ? c->max_hits_event : 1;
   if (n_tiles == 0) return hipSuccess;
+  static_assert(kRefineBlock == 8, "the refinement pass runs 8-step blocks");
   return c->field_kind == 0 ? launch_scan_t<float, 0, 8, 4, 1>(c, a, n_tiles, false, c->r_slab)
                             : launch_scan_t<float, 1, 8, 8, 1>(c, a, n_tiles, false, c->r_slab);
 }
@@ -1079,18 +1110,21 @@ trace_kernel(FieldDev f, double R0, double charge, double hstep, int turn_stop, 
   const R r0sq = (R)(R0 * R0);
   int n = 0;
   bool live = true;   // with turn_stop, states after the end of the turn partition stay
+  Prop<R, FIELD> pr;  // the scan's propagation, folded every kTraceFold steps
+  pr.start(st);
   for (int k = 0; k < n_sel; ++k) {
     const int target = steps[k];
     for (; n < target && live; ++n) {
-      rkn_step<R, FIELD>(st, f, f.nodes, h);
-      live = !(turn_stop && inside_r0(st.x, st.y, r0sq));
+      pr.step(st, f, f.nodes, h);
+      live = !(turn_stop && inside_r0(pr.px, pr.py, r0sq));
+      if ((n + 1) % kTraceFold == 0) pr.fold(st);
     }
-    o[6 * k + 0] = (double)st.x;
-    o[6 * k + 1] = (double)st.y;
-    o[6 * k + 2] = (double)st.z;
-    o[6 * k + 3] = (double)st.tx;
-    o[6 * k + 4] = (double)st.ty;
-    o[6 * k + 5] = (double)st.tz;
+    o[6 * k + 0] = (double)pr.px;
+    o[6 * k + 1] = (double)pr.py;
+    o[6 * k + 2] = (double)pr.pz;
+    o[6 * k + 3] = (double)pr.tx;
+    o[6 * k + 4] = (double)pr.ty;
+    o[6 * k + 5] = (double)pr.tz;
   }
 }
 

@@ -27,11 +27,11 @@ template <int FIELD>
 __global__ void __launch_bounds__(256)
 record_kernel(FieldDev f, const WindowDev* __restrict__ wins, const int64_t* __restrict__ win_base, int n_windows,
               int64_t s0, int64_t n, double R0, double charge, double hstep, int n_steps, int turn_stop,
-              float* __restrict__ traj, int32_t* __restrict__ seed_win) {
+              int fold, float* __restrict__ traj, int32_t* __restrict__ seed_win) {
   extern __shared__ float2 s_field[];
   const float2* nodes = f.nodes;
   if constexpr (FIELD == 1) {
-    const int nn = f.nr * f.nz;
+    const int nn = (int)padded_field_nodes(f.nr, f.nz);
     for (int i = threadIdx.x; i < nn; i += blockDim.x) s_field[i] = f.nodes[i];
     __syncthreads();
     nodes = s_field;
@@ -69,15 +69,23 @@ record_kernel(FieldDev f, const WindowDev* __restrict__ wins, const int64_t* __r
   out[0] = st.x;
   out[1] = st.y;
   out[2] = st.z;
-  bool live = true;
+  // the fused scan's propagation: block-relative sums folded at the ends of its
+  // blocks of `fold` steps (while the track was live at the block's start)
+  Prop<float, FIELD> pr;
+  pr.start(st);
+  bool live = true, live_blk = true;
   for (int j = 1; j <= n_steps; ++j) {
     if (live) {
-      rkn_step<float, FIELD>(st, f, nodes, h);
-      live = !(turn_stop && st.x * st.x + st.y * st.y < r0sq);
+      pr.step(st, f, nodes, h);
+      live = !(turn_stop && inside_r0(pr.px, pr.py, r0sq));
     }
-    out[3 * j + 0] = st.x;
-    out[3 * j + 1] = st.y;
-    out[3 * j + 2] = st.z;
+    if (j % fold == 0 || j == n_steps) {
+      if (live_blk) pr.fold(st);
+      live_blk = live;
+    }
+    out[3 * j + 0] = pr.px;
+    out[3 * j + 1] = pr.py;
+    out[3 * j + 2] = pr.pz;
   }
 }
 
@@ -278,7 +286,8 @@ rkn_status rkn_scan_windows_two_kernel(rkn_ctx* c, const rkn_scan_params* p, int
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_evs.p, ev_seed.data(), sizeof(int64_t) * ev_seed.size(), hipMemcpyHostToDevice, c->stream);
   const FieldDev f = field_dev(c);
-  const size_t smem = c->field_kind == 1 ? sizeof(float2) * (size_t)c->nr * c->nz : 0;
+  const int fold = resolve_block_steps(c, p);   // the fused scan's block: the same trajectories
+  const size_t smem = c->field_kind == 1 ? sizeof(float2) * padded_field_nodes(c->nr, c->nz) : 0;
   if (e == hipSuccess && c->field_kind == 1)
     e = hipFuncSetAttribute((const void*)record_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   for (int64_t s0 = 0; e == hipSuccess && s0 < total; s0 += chunk) {
@@ -286,11 +295,11 @@ rkn_status rkn_scan_windows_two_kernel(rkn_ctx* c, const rkn_scan_params* p, int
     const dim3 g1((unsigned)((m + 255) / 256)), b1(256);
     if (c->field_kind == 0)
       hipLaunchKernelGGL(record_kernel<0>, g1, b1, 0, c->stream, f, d_wins.as<WindowDev>(), d_base.as<int64_t>(),
-                         n_windows, s0, m, p->R0, p->charge, p->step_mm, p->n_steps, p->turn_stop,
+                         n_windows, s0, m, p->R0, p->charge, p->step_mm, p->n_steps, p->turn_stop, fold,
                          d_traj.as<float>(), d_swin.as<int32_t>());
     else
       hipLaunchKernelGGL(record_kernel<1>, g1, b1, smem, c->stream, f, d_wins.as<WindowDev>(), d_base.as<int64_t>(),
-                         n_windows, s0, m, p->R0, p->charge, p->step_mm, p->n_steps, p->turn_stop,
+                         n_windows, s0, m, p->R0, p->charge, p->step_mm, p->n_steps, p->turn_stop, fold,
                          d_traj.as<float>(), d_swin.as<int32_t>());
     if ((e = hipGetLastError()) != hipSuccess) break;
     hipLaunchKernelGGL(dca_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, c->stream, c->hits32.as<HitRec<float>>(),
