@@ -91,6 +91,8 @@ def lib():
                                           P, P, P, P, P]
         _lib.orc_scan_seeds.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int64, P, P, P, P, P, P,
                                         C.c_int32, P, P, P, P, P]
+        _lib.orc_rescan_refine.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_int32, C.c_int32, C.c_int32,
+                                           P, P, P, C.c_int32, P, P, P, P, P]
         _lib.orc_hough_accumulate.argtypes = [P, P, C.c_int32, P, P]
         _lib.orc_hough_peaks.argtypes = [P, P, C.c_int32, P, P]
         _lib.orc_hough_window.argtypes = [P, P, C.c_int64, P]
@@ -273,6 +275,27 @@ class Oracle:
         if pairs is not None:
             pairs.append(np_.value)
         return score, n_in, bi, bs
+
+    def rescan_refine(self, prm, ev_off, wire_id, drift, start5, step5, grid=6, max_rounds=10,
+                      target=None, mode=1):
+        """The paper's coarse-to-fine rescans (section 2.2) from the kept seeds start5 and
+        their grid steps step5 ([n_events][k][5]). Returns (seeds5, steps5, scores,
+        rounds, margin) per event."""
+        ev_off = np.ascontiguousarray(ev_off, np.int32); wire_id = np.ascontiguousarray(wire_id, np.int32)
+        drift = np.ascontiguousarray(drift, np.float32)
+        start5 = np.ascontiguousarray(start5, np.float64); step5 = np.ascontiguousarray(step5, np.float64)
+        ne, k = start5.shape[0], start5.shape[1]
+        assert start5.shape == (ne, k, 5) and step5.shape == (ne, k, 5) and ev_off.size == ne + 1
+        tg = None if target is None else np.ascontiguousarray(target, np.float64)
+        out5 = np.zeros((ne, k, 5)); ostep = np.zeros((ne, k, 5)); osc = np.zeros((ne, k))
+        rounds = np.zeros(ne, np.int32); margin = np.zeros(ne)
+        rc = lib().orc_rescan_refine(C.byref(self.geo), C.byref(self.field), C.byref(prm), ne, _ptr(ev_off),
+                                     _ptr(wire_id), _ptr(drift), k, int(grid), int(max_rounds), _ptr(start5),
+                                     _ptr(step5), None if tg is None else _ptr(tg), mode, _ptr(out5),
+                                     _ptr(ostep), _ptr(osc), _ptr(rounds), _ptr(margin))
+        if rc != 0:
+            raise ValueError("orc_rescan_refine: k >= 1, grid >= 2, max_rounds >= 0")
+        return out5, ostep, osc, rounds, margin
 
     # ---- Hough -------------------------------------------------------------------
     @staticmethod

@@ -1118,3 +1118,140 @@ double orc_score_adaptive(const orc_geometry *g, const orc_field *f, const orc_p
   if (n_in) *n_in = cnt;
   return E;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Section 2.2, the paper's refinement of a scan: the several seeds with the
+ * lowest E are kept, finer seed sets are built around them and the scan is
+ * repeated (ten times in the paper). Readings: a round builds, around each kept
+ * seed in the order they were kept, a grid of `grid` points per dimension whose
+ * half-width is the grid step the seed came from (a dimension whose step is 0 has
+ * one point); every seed of the round's grids is scored (Eq. 1) and the k lowest
+ * (E, then position in the round's window order) are kept, each with the step of
+ * its own grid, 2 half-width / (grid - 1). An event stops after the round whose
+ * lowest E is <= target[e] (never without a target), or after max_rounds. The
+ * margin of an event is the smallest relative gap, over its rounds, between
+ * consecutive E of the k + 1 lowest (pairs of one seed with one step excepted:
+ * they tie exactly in any scorer) and between the lowest E and the target: a
+ * scorer whose relative error stays below half of it makes every choice of the
+ * loop the same.                                                               */
+typedef struct {
+  double s;
+  int64_t i;
+} scored_seed;
+
+static int scored_order(const void *pa, const void *pb) {
+  const scored_seed *a = (const scored_seed *)pa, *b = (const scored_seed *)pb;
+  if (a->s < b->s) return -1;
+  if (a->s > b->s) return 1;
+  return a->i < b->i ? -1 : (a->i > b->i ? 1 : 0);
+}
+
+static double rel_gap(double a, double b) {
+  double d = fabs(a - b), m = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+  if (isinf(a) || isinf(b)) return a == b ? 0.0 : INFINITY;
+  return m > 0.0 ? d / m : 0.0;
+}
+
+int orc_rescan_refine(const orc_geometry *g, const orc_field *f, const orc_params *p,
+                      int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
+                      int32_t k, int32_t grid, int32_t max_rounds, const double *start5, const double *step5,
+                      const double *target, int32_t mode, double *out5, double *out_step5, double *out_score,
+                      int32_t *rounds, double *margin) {
+  int32_t e;
+  if (k < 1 || grid < 2 || max_rounds < 0) return -1;
+  for (e = 0; e < n_events; ++e) {
+    double *cur = out5 + (size_t)e * k * 5, *stp = out_step5 + (size_t)e * k * 5;
+    double *sc = out_score + (size_t)e * k;
+    const int32_t nh = ev_off[e + 1] - ev_off[e];
+    int32_t j, d, r;
+    memcpy(cur, start5 + (size_t)e * k * 5, sizeof(double) * 5 * k);
+    memcpy(stp, step5 + (size_t)e * k * 5, sizeof(double) * 5 * k);
+    for (j = 0; j < k; ++j) sc[j] = NAN;
+    rounds[e] = 0;
+    if (margin) margin[e] = INFINITY;
+    for (r = 0; r < max_rounds; ++r) {
+      orc_window *w = (orc_window *)calloc((size_t)k, sizeof(orc_window));
+      int64_t *base = (int64_t *)malloc(sizeof(int64_t) * (k + 1));
+      int32_t nw = 0, q;
+      int64_t total, s;
+      scored_seed *all;
+      for (j = 0; j < k; ++j) {
+        int ok = 1;
+        for (d = 0; d < 5; ++d) ok = ok && isfinite(cur[j * 5 + d]) && isfinite(stp[j * 5 + d]);
+        if (!ok) continue;
+        w[nw].event = e;
+        w[nw].candidate = nw;
+        for (d = 0; d < 5; ++d) {
+          w[nw].center[d] = cur[j * 5 + d];
+          w[nw].half_width[d] = stp[j * 5 + d];
+          w[nw].count[d] = stp[j * 5 + d] > 0.0 ? grid : 1;
+        }
+        ++nw;
+      }
+      if (nw == 0) {
+        free(w);
+        free(base);
+        break;
+      }
+      base[0] = 0;
+      for (q = 0; q < nw; ++q) base[q + 1] = base[q] + window_size(&w[q]);
+      total = base[nw];
+      all = (scored_seed *)malloc(sizeof(scored_seed) * (size_t)total);
+#pragma omp parallel for schedule(static)
+      for (s = 0; s < total; ++s) {
+        int32_t kw = 0;
+        double seed[5];
+        while (base[kw + 1] <= s) ++kw;
+        orc_window_seed(&w[kw], s - base[kw], seed);
+        all[s].s = orc_score(g, f, p, seed, nh, wire_id + ev_off[e], drift + ev_off[e], mode, NULL, NULL);
+        all[s].i = s;
+      }
+      qsort(all, (size_t)total, sizeof(scored_seed), scored_order);
+      for (j = 0; j < k; ++j) {
+        if (j < total) {
+          int32_t kw = 0;
+          int64_t gi = all[j].i;
+          while (base[kw + 1] <= gi) ++kw;
+          orc_window_seed(&w[kw], gi - base[kw], cur + j * 5);
+          for (d = 0; d < 5; ++d)
+            stp[j * 5 + d] = w[kw].count[d] > 1 ? 2.0 * w[kw].half_width[d] / (double)(w[kw].count[d] - 1) : 0.0;
+          sc[j] = all[j].s;
+        } else {
+          for (d = 0; d < 5; ++d) cur[j * 5 + d] = stp[j * 5 + d] = NAN;
+          sc[j] = NAN;
+        }
+      }
+      rounds[e] = r + 1;
+      if (margin) {
+        /* consecutive pairs of the k + 1 lowest: their order decides the kept set and
+         * the next round's window order (equal seeds tie exactly in any scorer) */
+        double mg = margin[e];
+        for (j = 0; j < k && j + 1 < total; ++j) {
+          double sa[5], sb[5];
+          int32_t ka = 0, kb = 0;
+          while (base[ka + 1] <= all[j].i) ++ka;
+          while (base[kb + 1] <= all[j + 1].i) ++kb;
+          orc_window_seed(&w[ka], all[j].i - base[ka], sa);
+          orc_window_seed(&w[kb], all[j + 1].i - base[kb], sb);
+          if (memcmp(sa, sb, sizeof(sa)) != 0 || memcmp(&w[ka].half_width, &w[kb].half_width, sizeof(sa)) != 0) {
+            double gk = rel_gap(all[j + 1].s, all[j].s);
+            if (gk < mg) mg = gk;
+          }
+        }
+        if (target) {
+          double gt = rel_gap(all[0].s, target[e]);
+          if (gt < mg) mg = gt;
+        }
+        margin[e] = mg;
+      }
+      {
+        const double best = all[0].s;
+        free(all);
+        free(w);
+        free(base);
+        if (target && best <= target[e]) break;
+      }
+    }
+  }
+  return 0;
+}

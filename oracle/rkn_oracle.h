@@ -100,6 +100,24 @@ int orc_scan_seeds(const orc_geometry *g, const orc_field *f, const orc_params *
                    double *score, int32_t *n_in, int64_t *best_index, double *best_score,
                    int64_t *pairs_total);
 
+/* ---- Section 2.2: the coarse-to-fine rescans that refine a scan's best seeds ----
+ * Per event, rounds of: a grid of `grid` points per dimension around each of the k
+ * kept seeds (half-width = the step of the grid the seed came from; one point where
+ * that step is 0), every seed scored (Eq. 1, `mode` as orc_score), the k lowest
+ * (E, then position in the round) kept with their own grid step. start5/step5
+ * [n_events][k][5] are the first kept seeds and steps (a row with a non-finite
+ * value is no seed). Stops after the round whose lowest E <= target[e] (target may
+ * be NULL) or after max_rounds. Outputs: out5/out_step5 [n_events][k][5] and
+ * out_score [n_events][k] (NaN rows: no seed), rounds [n_events], margin
+ * [n_events] (optional): the smallest relative gap between consecutive E of the
+ * k + 1 lowest of a round (pairs of one seed with one step excepted) and between
+ * the lowest E and the target. Returns 0, or -1 for k < 1, grid < 2, max_rounds < 0. */
+int orc_rescan_refine(const orc_geometry *g, const orc_field *f, const orc_params *p,
+                      int32_t n_events, const int32_t *ev_off, const int32_t *wire_id, const float *drift,
+                      int32_t k, int32_t grid, int32_t max_rounds, const double *start5, const double *step5,
+                      const double *target, int32_t mode, double *out5, double *out_step5, double *out_score,
+                      int32_t *rounds, double *margin);
+
 /* ---- Section 2.1: circle Hough transform over the wire (x, y) positions ---- */
 typedef struct {
   int32_t n_xy, n_r;                  /* accumulator n_xy x n_xy x n_r */
