@@ -310,6 +310,39 @@ rkn_status rkn_batch_info(rkn_ctx *ctx, int32_t *n_windows, int64_t *n_seeds, fl
 rkn_status rkn_batch_results(rkn_ctx *ctx, int32_t max_windows, rkn_window *windows, int32_t *n_windows,
                              int64_t max_seeds, double *score, int32_t *n_in, int64_t *ev_seed_off);
 
+/* ---- Coarse-to-fine rescans (section 2.2) --------------------------------------------
+ * The paper's refinement of a scan: the seeds with the lowest E are kept, finer seed
+ * sets are built around them and the scan is repeated (ten times in the paper). Per
+ * event and round: around each kept seed, in the order they were kept, a grid of
+ * `grid` points per dimension whose half-width is the grid step that seed came from
+ * (one point in a dimension whose step is 0); every seed of the event's grids is
+ * scored as by rkn_scan_windows (p: precision, steps, lambda, turn_stop); the k
+ * lowest (E, then position in the round: grid order, theta slowest within a grid)
+ * are kept, each with the step of its own grid, 2 half-width / (grid - 1). An event
+ * stops after the round whose lowest E is <= target[e], or after max_rounds. Every
+ * round runs on the context's stream with no host synchronisation in between: the
+ * grids, the seed tiles and the selection are built on the device. */
+typedef struct {
+  int32_t k;           /* seeds kept per event, 1..RKN_TOPK_MAX                       */
+  int32_t grid;        /* points per dimension of a round's grids, 2..16              */
+  int32_t max_rounds;  /* rounds at most, 0..64                                       */
+  int32_t reserved;    /* 0                                                           */
+} rkn_rescan_params;
+
+/* start5 / step5 [n_events][k][5]: the first kept seeds and the steps of the grids they
+ * came from (a row with a non-finite value holds no seed); both NULL: the k lowest
+ * seeds of the last rkn_batch_launch with the steps of their windows (RKN_E_STATE if
+ * nothing was launched since the last upload). target [n_events] or NULL (every event
+ * runs max_rounds rounds). Inputs and outputs are host or device pointers per
+ * p->ptr_flags. Outputs (each may be NULL): out5 / out_step5 [n_events][k][5] and
+ * out_score [n_events][k] (NaN rows: no seed; NaN scores for an event that ran no
+ * round), rounds [n_events] (rounds run). A round scans up to n_events * k * grid^5
+ * seeds (RKN_E_CAPACITY above 2^32); its per-seed scores stay in context-owned
+ * device memory. RKN_E_UNSUPPORTED for a scan shape that does not fit the device. */
+rkn_status rkn_rescan_refine(rkn_ctx *ctx, const rkn_scan_params *p, const rkn_rescan_params *rp,
+                             const double *start5, const double *step5, const double *target,
+                             double *out5, double *out_step5, double *out_score, int32_t *rounds);
+
 /* ---- Hit classification and the two-direction quality count -----------------------
  * Section 2.2: a hit belongs to a seed's track when (D - d)^2 < lambda; the scan is
  * run independently from seed sets at the chamber entrance and at its exit, and a

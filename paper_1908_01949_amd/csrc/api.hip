@@ -73,6 +73,19 @@ rkn_status check_state(rkn_ctx* c) {
   return RKN_OK;
 }
 
+}  // namespace
+
+namespace rkn {
+
+rkn_status validate_scan(rkn_ctx* c, const rkn_scan_params* p) {
+  const rkn_status st = check_scan_params(c, p);
+  return st != RKN_OK ? st : check_state(c);
+}
+
+}  // namespace rkn
+
+namespace {
+
 // Copy a device result to caller memory (host or device per ptr_flags).
 template <typename T>
 hipError_t deliver(rkn_ctx* c, T* dst, const T* dsrc, size_t n, bool dev) {
@@ -129,6 +142,7 @@ void rkn_destroy(rkn_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   rkn::batch_release(c);
   c->refine_release();
+  rkn::rescan_release(c);
   DevBuf* bufs[] = {&c->wire32, &c->wire64, &c->wire_layer, &c->layer_r, &c->field_nodes, &c->ev_off,
                     &c->hits32, &c->hits64, &c->layer_off, &c->ev_maxdrift, &c->windows, &c->tiles,
                     &c->ev_tiles, &c->parts, &c->counter, &c->mscratch, &c->out_score, &c->out_nin,

@@ -168,6 +168,11 @@ struct rkn_ctx {
   rkn::DevBuf b_slab, b_parts, b_counter;
   void* b_hough_ptrs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
+  // coarse-to-fine rescans (rescan.hip): kept seeds, per-round windows and scores
+  rkn::DevBuf rs_cur, rs_step, rs_score, rs_rounds, rs_active, rs_target, rs_windows, rs_tiles, rs_ev_tiles,
+      rs_ev_seed, rs_ev_win, rs_counts, rs_ev_scratch, rs_seed_score, rs_best_i, rs_best_e, rs_sel_idx, rs_sel_sc,
+      rs_sel_seed, rs_sel_step, rs_parts, rs_counter, rs_slab;
+
   // refinement (refine.hip): seeds grouped by event, inlier sets fixed at setup
   bool r_ready = false;
   rkn_scan_params r_params{};
@@ -229,14 +234,31 @@ void batch_release(rkn_ctx* c);
 // The k lowest-score seeds of each of n_seg events (select.hip): seeds of event e
 // are d_score[d_seg_off[e] .. d_seg_off[e+1]) and come from windows
 // d_win_off[e] .. (e + 1 < n_seg ? d_win_off[e+1] : *d_win_total), in order.
+// d_seed / d_step (optional): each pick's seed and the grid step of its window.
 hipError_t launch_topk(rkn_ctx* c, const double* d_score, const long long* d_seg_off, const WindowDev* d_windows,
                        const int32_t* d_win_off, int n_seg, const int32_t* d_win_total, int k, int64_t* d_idx,
-                       double* d_sc, double* d_seed);
+                       double* d_sc, double* d_seed, double* d_step = nullptr);
 
-// Scan launch whose tile count is read from device memory (batched path; uses the
-// batch's private scratch b_slab, b_parts, b_counter).
+// Scratch of one user of launch_scan_dev: argmin partials, tile counter, slab.
+struct ScanScratch {
+  DevBuf* parts;
+  DevBuf* counter;
+  DevBuf* slab;
+};
+
+// Scan launch whose tile count is read from device memory (no host synchronisation;
+// capturable once the scratch is sized). The batched path uses its private scratch
+// b_slab, b_parts, b_counter; other users pass their own.
 hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_tiles, const int32_t* d_n_tiles,
                            const Tile* d_tiles, const WindowDev* d_windows, double* d_score, int32_t* d_nin,
-                           int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only);
+                           int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only,
+                           const ScanScratch* scratch = nullptr);
+
+// Release the rescan loop's buffers (rescan.hip).
+void rescan_release(rkn_ctx* c);
+
+// Scan parameters valid and geometry, field and hits uploaded (api.hip); sets the
+// error text otherwise.
+rkn_status validate_scan(rkn_ctx* c, const rkn_scan_params* p);
 
 }  // namespace rkn

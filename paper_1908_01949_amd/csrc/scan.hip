@@ -1066,18 +1066,21 @@ hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, co
 
 hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_tiles, const int32_t* d_n_tiles,
                            const Tile* d_tiles, const WindowDev* d_windows, double* d_score, int32_t* d_nin,
-                           int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only) {
-  hipError_t e = c->b_parts.ensure(sizeof(ArgminPart) * (size_t)(max_tiles > 0 ? max_tiles : 1));
+                           int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only,
+                           const ScanScratch* scratch) {
+  const ScanScratch own{&c->b_parts, &c->b_counter, &c->b_slab};
+  const ScanScratch& s = scratch ? *scratch : own;
+  hipError_t e = s.parts->ensure(sizeof(ArgminPart) * (size_t)(max_tiles > 0 ? max_tiles : 1));
   if (e != hipSuccess) return e;
-  e = c->b_counter.ensure(64);
+  e = s.counter->ensure(64);
   if (e != hipSuccess) return e;
-  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, c->b_parts, c->b_counter);
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, *s.parts, *s.counter);
   a.n_tiles = max_tiles;
   a.n_tiles_dev = d_n_tiles;
-  e = dispatch_scan(c, p, a, max_tiles, alloc_only, c->b_slab);
+  e = dispatch_scan(c, p, a, max_tiles, alloc_only, *s.slab);
   if (e != hipSuccess || alloc_only) return e;
   hipLaunchKernelGGL(event_argmin_kernel, dim3(c->n_events), dim3(256), 0, c->stream,
-                     c->b_parts.as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
+                     s.parts->as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(256)
 topk_kernel(const double* __restrict__ score, const long long* __restrict__ seg_off,
             const WindowDev* __restrict__ windows, const int32_t* __restrict__ win_off, int n_seg,
             const int32_t* __restrict__ win_total, int k, int64_t* __restrict__ out_idx,
-            double* __restrict__ out_score, double* __restrict__ out_seed) {
+            double* __restrict__ out_score, double* __restrict__ out_seed, double* __restrict__ out_step) {
   const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long lo = seg_off[e], hi = seg_off[e + 1];
   double bs[kTopMax];
@@ -100,8 +100,8 @@ topk_kernel(const double* __restrict__ score, const long long* __restrict__ seg_
     const size_t o = (size_t)e * k + tid;
     out_idx[o] = g;
     out_score[o] = s_sc[tid];
-    double v[5] = {NAN, NAN, NAN, NAN, NAN};
-    if (g >= 0 && out_seed) {
+    double v[5] = {NAN, NAN, NAN, NAN, NAN}, st[5] = {NAN, NAN, NAN, NAN, NAN};
+    if (g >= 0 && (out_seed || out_step)) {
       const int w0 = win_off[e];
       const int w1 = e + 1 < n_seg ? win_off[e + 1] : *win_total;
       long long local = g - lo;
@@ -110,6 +110,10 @@ topk_kernel(const double* __restrict__ score, const long long* __restrict__ seg_
         for (int d = 0; d < 5; ++d) size *= windows[w].count[d];
         if (local < size) {
           window_seed(windows[w], local, v);
+          // the step of the grid the seed came from (0 where the window has one point)
+          for (int d = 0; d < 5; ++d)
+            st[d] = windows[w].count[d] > 1 ? 2.0 * windows[w].half_width[d] / (double)(windows[w].count[d] - 1)
+                                            : 0.0;
           break;
         }
         local -= size;
@@ -117,16 +121,18 @@ topk_kernel(const double* __restrict__ score, const long long* __restrict__ seg_
     }
     if (out_seed)
       for (int d = 0; d < 5; ++d) out_seed[o * 5 + d] = v[d];
+    if (out_step)
+      for (int d = 0; d < 5; ++d) out_step[o * 5 + d] = st[d];
   }
 }
 
 hipError_t launch_topk(rkn_ctx* c, const double* d_score, const long long* d_seg_off, const WindowDev* d_windows,
                        const int32_t* d_win_off, int n_seg, const int32_t* d_win_total, int k, int64_t* d_idx,
-                       double* d_sc, double* d_seed) {
+                       double* d_sc, double* d_seed, double* d_step) {
   if (n_seg <= 0) return hipSuccess;
   if (k < 1 || k > kTopMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(topk_kernel, dim3(n_seg), dim3(256), 0, c->stream, d_score, d_seg_off, d_windows, d_win_off,
-                     n_seg, d_win_total, k, d_idx, d_sc, d_seed);
+                     n_seg, d_win_total, k, d_idx, d_sc, d_seed, d_step);
   return hipGetLastError();
 }
 

@@ -70,6 +70,14 @@ class rkn_turn_params(C.Structure):
 RKN_TURNS_MAX = 16
 
 
+class rkn_rescan_params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("grid", C.c_int32), ("max_rounds", C.c_int32), ("reserved", C.c_int32)]
+
+
+def make_rescan_params(k=8, grid=6, max_rounds=10) -> rkn_rescan_params:
+    return rkn_rescan_params(int(k), int(grid), int(max_rounds), 0)
+
+
 class rkn_adaptive_params(C.Structure):
     _fields_ = [("tol_mm", C.c_double), ("h_min_mm", C.c_double), ("h_max_mm", C.c_double)]
 
@@ -117,6 +125,7 @@ _SIGS = {
     "rkn_scan_windows_two_kernel": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
     "rkn_scan_windows_adaptive": (C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P]),
     "rkn_batch_plan_adaptive": (C.c_int32, [_P, _P, _P, _P]),
+    "rkn_rescan_refine": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -380,6 +389,29 @@ def rkn_batch_topk(ctx, k, index=None, score=None, seeds5=None, n_events=None):
         seeds5 = np.zeros((n_events, k, 5))
     _check(ctx, load_library().rkn_batch_topk(ctx, int(k), _ptr(index), _ptr(score), _ptr(seeds5)))
     return index, score, seeds5
+
+
+def rkn_rescan_refine(ctx, p: rkn_scan_params, rp: rkn_rescan_params, n_events: int, start5=None, step5=None,
+                      target=None, out5=None, out_step5=None, out_score=None, rounds=None):
+    """The coarse-to-fine rescans (start5/step5 None: from the last batch launch's k
+    best). With host pointers, outputs are allocated when None and returned as
+    (seeds5, steps5, scores, rounds)."""
+    k = rp.k
+    dev = bool(p.ptr_flags & 1)
+    if not dev:
+        if start5 is not None:
+            start5 = np.ascontiguousarray(start5, np.float64).reshape(n_events, k, 5)
+            step5 = np.ascontiguousarray(step5, np.float64).reshape(n_events, k, 5)
+        if target is not None:
+            target = np.ascontiguousarray(target, np.float64).reshape(n_events)
+        out5 = np.zeros((n_events, k, 5)) if out5 is None else out5
+        out_step5 = np.zeros((n_events, k, 5)) if out_step5 is None else out_step5
+        out_score = np.zeros((n_events, k)) if out_score is None else out_score
+        rounds = np.zeros(n_events, np.int32) if rounds is None else rounds
+    _check(ctx, load_library().rkn_rescan_refine(ctx, C.byref(p), C.byref(rp), _ptr(start5), _ptr(step5),
+                                                 _ptr(target), _ptr(out5), _ptr(out_step5), _ptr(out_score),
+                                                 _ptr(rounds)))
+    return out5, out_step5, out_score, rounds
 
 
 def rkn_batch_info(ctx):

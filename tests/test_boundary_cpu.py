@@ -50,7 +50,7 @@ def test_struct_layouts_match_c_compiler(tmp_path):
     from paper_1908_01949_amd import rknscan
     structs = {"rkn_window": rknscan.rkn_window, "rkn_scan_params": rknscan.rkn_scan_params,
                "rkn_hough_params": rknscan.rkn_hough_params, "rkn_turn_params": rknscan.rkn_turn_params,
-               "rkn_adaptive_params": rknscan.rkn_adaptive_params}
+               "rkn_adaptive_params": rknscan.rkn_adaptive_params, "rkn_rescan_params": rknscan.rkn_rescan_params}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rknscan.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
