@@ -121,20 +121,17 @@ def _sync_time(fn):
 
 
 def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rtol=1e-3,
-               scale=(1.0, 100.0, 100.0, 100.0, 100.0)):
+               scale=(1.0, 100.0, 100.0, 100.0, 100.0), grid=6):
     """Refinement of the k best seeds per event of the batch just scanned, two ways:
     (a) Gauss-Newton with the adjoint sweep (gn_iters iterations), and (b) the paper's
-    coarse-to-fine rescans (section 2.2): 6^5 grids around the current k best seeds
-    whose half-width is the previous grid step, the k best of each round kept, until
-    the best seed's Phi on the inlier set of the event's best Gauss-Newton seed is
-    within (1 + rtol) of that seed's Phi, or max_rounds. Both legs include the shared
-    coarse scan time; the Phi checks of (b) are not timed."""
-    import torch
+    coarse-to-fine rescans (section 2.2) through rkn_rescan_refine: grid^5 grids around
+    the k kept seeds, half-width = the previous grid step, max_rounds rounds. (b) runs
+    twice: all rounds, as the paper does, and stopping each event once its lowest E is
+    within rtol * Phi_GN of the E of its best Gauss-Newton seed (the same residual
+    accuracy in mm^2). Times include the shared coarse scan; the targets and the
+    accuracy checks are not timed."""
     ne = n_events
     (idx, sc, s5), t_topk = _sync_time(lambda: rk.rkn_batch_topk(ctx.ctx, k, n_events=ne))
-    windows, _, _, ev_seed = rk.rkn_batch_results(ctx.ctx, ne, want_scores=False)
-    sizes = np.prod(windows["count"].astype(np.int64), axis=1)
-    wbase = np.concatenate([[0], np.cumsum(sizes)])
     ok = idx >= 0
     ev_of = np.repeat(np.arange(ne, dtype=np.int32), k).reshape(ne, k)
     seed_event = ev_of[ok]
@@ -163,6 +160,14 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
     phi_gn = np.where(has, phi_fin[np.maximum(best_slot, 0)], np.nan)
     log(f"refine: {nsd} seeds, top-{k} {t_topk * 1e3:.1f} ms, GN {gn_iters} it {t_gn * 1e3:.1f} ms, "
         f"Phi {np.nanmean(gn_phi[:, 0]):.3g} -> {np.nanmean(phi_fin):.3g}")
+    # E of each event's best GN seed (untimed): the rescans' target in their own score
+    e_gn = np.full(ne, np.inf)
+    if has.any():
+        ev_h = np.nonzero(has)[0].astype(np.int32)
+        sc_gn, _, _, _ = rk.rkn_scan_seeds(ctx.ctx, sp, ev_h, gn_seeds[best_slot[has]], np.zeros(ev_h.size),
+                                           np.zeros(ev_h.size, np.int32), np.zeros(ne, np.int64), np.zeros(ne))
+        e_gn[has] = sc_gn
+    target = np.where(has, e_gn + rtol * phi_gn, -np.inf)
 
     def phi_on_gn_set(cand):
         """Phi of cand[e] on the inlier set of event e's best GN seed (not timed)."""
@@ -175,77 +180,49 @@ def refine_leg(ctx, sp, n_events, t_coarse, k=8, gn_iters=10, max_rounds=10, rto
         out[sel] = ph[best_slot[sel]]
         return out
 
-    # (b) rescans: the previous grid step of each coarse pick is its window's step
-    kw = np.searchsorted(wbase, np.where(ok, idx, 0), side="right") - 1
-    cnt = windows["count"][kw].astype(np.float64)
-    step = np.where(cnt > 1, 2.0 * windows["half_width"][kw] / np.maximum(cnt - 1, 1), 0.0)
-    cur = s5.copy()
-    cur_ok = ok.copy()
-    active = has.copy()
-    rounds = np.zeros(ne, np.int64)
-    reached = np.zeros(ne, bool)
-    t_rounds = 0.0
-    seeds_scanned = 0
-    for r in range(max_rounds):
-        ev_act = np.nonzero(active)[0]
-        if ev_act.size == 0:
-            break
-        rows = [(e, j) for e in ev_act for j in range(k) if cur_ok[e, j]]
-        w = np.zeros(len(rows), synth.WINDOW_DTYPE)
-        ee = np.array([e for e, _ in rows]); jj = np.array([j for _, j in rows])
-        w["event"] = ee
-        w["candidate"] = jj
-        w["center"] = cur[ee, jj]
-        w["half_width"] = step[ee, jj]
-        w["count"] = 6
-        (nidx, nsc, ns5), dt = _sync_time(lambda: rk.rkn_scan_windows_topk(ctx.ctx, sp, w, k, n_events=ne))
-        t_rounds += dt
-        seeds_scanned += len(rows) * 6 ** 5
-        # the k best of this rescan, each with the step of the grid it came from
-        widx = np.zeros(ne, np.int64)
-        wsz = 6 ** 5
-        first_row = np.full(ne, -1)
-        for i, e in enumerate(ee):
-            if first_row[e] < 0:
-                first_row[e] = i
-        gb = np.zeros(ne, np.int64)
-        acc = 0
-        for e in range(ne):
-            gb[e] = acc
-            acc += int((ee == e).sum()) * wsz
-        new_step = np.zeros_like(step)
-        for e in ev_act:
-            for j in range(k):
-                g = nidx[e, j]
-                if g < 0:
-                    cur_ok[e, j] = False
-                    continue
-                row = first_row[e] + (g - gb[e]) // wsz
-                new_step[e, j] = 2.0 * w["half_width"][row] / 5.0
-                cur[e, j] = ns5[e, j]
-                cur_ok[e, j] = True
-        step = np.where(active[:, None, None], new_step, step)
-        rounds[ev_act] += 1
-        ph = phi_on_gn_set(ns5[:, 0, :])
-        done = active & (ph <= (1.0 + rtol) * phi_gn)
-        reached |= done
-        active &= ~done
-        log(f"rescan round {r + 1}: {len(rows)} windows, {dt * 1e3:.1f} ms, {int(done.sum())} events reached, "
-            f"{int(active.sum())} left")
+    # (b) the paper's rescans from the batch's k best, all rounds, then with the stop rule
+    rp = rk.make_rescan_params(k=k, grid=grid, max_rounds=max_rounds)
+    (r5, rstep, rsc, rrounds), t_full = _sync_time(lambda: rk.rkn_rescan_refine(ctx.ctx, sp, rp, ne))
+    (q5, qstep, qsc, qrounds), t_stop = _sync_time(
+        lambda: rk.rkn_rescan_refine(ctx.ctx, sp, rp, ne, target=target))
+    full_reach_e = int(np.sum(has & (rsc[:, 0] <= target)))
+    stop_reach_e = int(np.sum(has & (qsc[:, 0] <= target)))
+    ph_full = phi_on_gn_set(r5[:, 0, :])
+    ph_stop = phi_on_gn_set(q5[:, 0, :])
+    full_reach_phi = int(np.sum(has & (ph_full <= (1.0 + rtol) * phi_gn)))
+    stop_reach_phi = int(np.sum(has & (ph_stop <= (1.0 + rtol) * phi_gn)))
+    valid0 = ok.sum(axis=1)
+    per_grid = grid ** 5
+
+    def seeds_scanned(rounds):
+        r = rounds.astype(np.int64)
+        return int(np.sum(np.where(r > 0, valid0 + (r - 1) * k, 0)) * per_grid)
+    log(f"rescans: all {max_rounds} rounds {t_full * 1e3:.1f} ms (E within target: {full_reach_e} events, "
+        f"Phi: {full_reach_phi}); with the stop rule {t_stop * 1e3:.1f} ms, mean rounds "
+        f"{qrounds[has].mean():.2f} (E: {stop_reach_e}, Phi: {stop_reach_phi})")
     t_a = t_coarse + t_topk + t_gn
-    t_b = t_coarse + t_topk + t_rounds
+    t_b = t_coarse + t_full
+    t_c = t_coarse + t_stop
     return dict(
         seeds=int(nsd), k=k, gn_iters=gn_iters, ckpt_every=ckpt, ckpt_tune_ms=[round(x, 3) for x in tune_ms],
         ms_coarse=round(t_coarse * 1e3, 2), ms_topk=round(t_topk * 1e3, 2), ms_gn=round(t_gn * 1e3, 2),
-        ms_rescans=round(t_rounds * 1e3, 2), rescan_seeds=int(seeds_scanned),
-        events_per_s_gn=ne / t_a, events_per_s_rescan=ne / t_b, speedup=t_b / t_a,
-        # the coarse scan and the top-k are shared: the refinement stages alone, and the
-        # end-to-end ratio a zero-cost refinement would reach
-        refinement_stage_speedup=t_rounds / t_gn, speedup_bound_shared_coarse=t_b / (t_coarse + t_topk),
-        rescan_rounds_mean=float(rounds[has].mean()) if has.any() else 0.0,
-        events_reached=int(reached.sum()), events_with_seeds=int(has.sum()),
+        rescan_grid=f"{grid}^5", ms_rescans_all_rounds=round(t_full * 1e3, 2),
+        ms_rescans_stopped=round(t_stop * 1e3, 2), rescan_seeds_all_rounds=seeds_scanned(rrounds),
+        rescan_seeds_stopped=seeds_scanned(qrounds),
+        events_per_s_gn=ne / t_a, events_per_s_rescan_all_rounds=ne / t_b, events_per_s_rescan_stopped=ne / t_c,
+        speedup_vs_paper_rescans=t_b / t_a, speedup_vs_stopped_rescans=t_c / t_a,
+        # the coarse scan is shared: the refinement stages alone, and the end-to-end
+        # ratio a zero-cost refinement would reach against the paper's ten rounds
+        refinement_stage_speedup=t_full / (t_topk + t_gn),
+        speedup_bound_shared_coarse=t_b / t_coarse,
+        rescan_rounds_mean_stopped=float(qrounds[has].mean()) if has.any() else 0.0,
+        events_with_seeds=int(has.sum()),
+        events_reaching_gn_e_all_rounds=full_reach_e, events_reaching_gn_e_stopped=stop_reach_e,
+        events_reaching_gn_phi_all_rounds=full_reach_phi, events_reaching_gn_phi_stopped=stop_reach_phi,
         phi_gn_mean=float(np.nanmean(phi_gn)), phi_start_mean=float(np.nanmean(gn_phi[:, 0])),
-        rule=f"rescans stop per event when Phi <= (1+{rtol:g}) Phi_GN on the GN inlier set, <= {max_rounds} rounds")
+        rule=f"stopped rescans end an event once its lowest E <= E(best GN seed) + {rtol:g} Phi_GN; "
+             f"reach counts: E by that rule, Phi as Phi(best rescan seed) <= (1+{rtol:g}) Phi_GN on the GN "
+             f"inlier set; <= {max_rounds} rounds")
 
 
 def bidirectional_leg(ctx, field, sp, n_events, t_entrance, n_hits_max, n_c_min=20):

@@ -206,9 +206,13 @@ __device__ __forceinline__ void advance(State<R>& st, R dx, R dy, R dz) {
 // changes d[0..2] of the position and d[3..5] of the direction over a step h.
 // FIELD 0: uniform B_z; FIELD 1: (r, z) map, where the field is evaluated already
 // scaled by lam (k = t x (lam B)) and r2 = px^2 + py^2 comes from the caller.
+// With the map, b1 (if not NULL) is lam B at p, taken as given instead of evaluated,
+// and b4 (if not NULL) receives lam B at the last stage's point
+// p + h t + h^2/2 k3.
 template <typename R, int FIELD>
 __device__ __forceinline__ void rkn_delta(const FieldDev& f, const float2* nodes, R lam, R h, R px, R py, R pz,
-                                          R tx, R ty, R tz, R r2, R d[6]) {
+                                          R tx, R ty, R tz, R r2, R d[6], const R* b1 = nullptr,
+                                          R* b4 = nullptr) {
   const R h2 = (R)0.5 * h, hh6 = h * h / (R)6, h6 = h / (R)6;
   if constexpr (FIELD == 0) {
     const R a = lam * (R)f.bz;
@@ -227,7 +231,13 @@ __device__ __forceinline__ void rkn_delta(const FieldDev& f, const float2* nodes
     d[5] = (R)0;
   } else {
     R bx, by, bz;   // lam B
-    field_rz_r2(f, nodes, px, py, pz, r2, lam, bx, by, bz);
+    if (b1) {
+      bx = b1[0];
+      by = b1[1];
+      bz = b1[2];
+    } else {
+      field_rz_r2(f, nodes, px, py, pz, r2, lam, bx, by, bz);
+    }
     const R k1x = ty * bz - tz * by;
     const R k1y = tz * bx - tx * bz;
     const R k1z = tx * by - ty * bx;
@@ -254,6 +264,11 @@ __device__ __forceinline__ void rkn_delta(const FieldDev& f, const float2* nodes
     const R k4x = t4y * bz - t4z * by;
     const R k4y = t4z * bx - t4x * bz;
     const R k4z = t4x * by - t4y * bx;
+    if (b4) {
+      b4[0] = bx;
+      b4[1] = by;
+      b4[2] = bz;
+    }
     d[0] = h * tx + hh6 * (k1x + k2x + k3x);
     d[1] = h * ty + hh6 * (k1y + k2y + k3y);
     d[2] = h * tz + hh6 * (k1z + k2z + k3z);
@@ -287,11 +302,22 @@ __device__ __forceinline__ void rkn_step(State<R>& st, const FieldDev& f, const 
 // indices (the ends of the scan's cull blocks), so every kernel that recomputes a
 // trajectory reproduces it exactly. In FP64 every step is a plain add into p and t
 // (the oracle's sums) and fold() stores them.
+//
+// FP32 with the field map: the first stage of a step takes the field of the previous
+// step's last stage, whose point p_n + h t_n + h^2/2 k3 lies (h^2/6) |2 k3 - k1 - k2|
+// ~ h^3 |lam B|^2 / 6 ~ 1e-6 mm from p_{n+1}: below the FP32 spacing of positions
+// there (3e-5 mm at 500 mm), so both points are mostly the same FP32 point, and the
+// field's change over that distance (< 2e-10 relative in the solenoid map) is far
+// below the FP32 rounding of the field itself. The field is evaluated at the seed
+// (init_field) and wherever a caller restarts a trajectory from a stored state (the
+// checkpoints of the refinement pass); fold() keeps it.
 template <typename R, int FIELD>
 struct Prop {
+  static constexpr bool kReuse = sizeof(R) == 4 && FIELD == 1;
   R px, py, pz, tx, ty, tz;   // current position and direction
   R qx, qy, qz, ux, uy, uz;   // increments since the block started (FP32)
   R r2;                       // px^2 + py^2
+  R fb[3];                    // lam B at the current point (FP32 map)
   __device__ __forceinline__ void start(const State<R>& s) {
     px = s.x;
     py = s.y;
@@ -302,9 +328,14 @@ struct Prop {
     qx = qy = qz = ux = uy = uz = (R)0;
     r2 = radius2(px, py);
   }
+  // lam B evaluated at the current point (FP32 map; nothing otherwise)
+  __device__ __forceinline__ void init_field(const State<R>& s, const FieldDev& f, const float2* nodes) {
+    if constexpr (kReuse) field_rz_r2(f, nodes, px, py, pz, r2, s.lam, fb[0], fb[1], fb[2]);
+  }
   __device__ __forceinline__ void step(const State<R>& s, const FieldDev& f, const float2* nodes, R h) {
     R d[6];
-    rkn_delta<R, FIELD>(f, nodes, s.lam, h, px, py, pz, tx, ty, tz, r2, d);
+    rkn_delta<R, FIELD>(f, nodes, s.lam, h, px, py, pz, tx, ty, tz, r2, d, kReuse ? fb : nullptr,
+                        kReuse ? fb : nullptr);
     if constexpr (sizeof(R) == 4) {
       qx += d[0];
       qy += d[1];

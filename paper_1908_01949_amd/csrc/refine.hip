@@ -335,6 +335,7 @@ __global__ void __launch_bounds__(64) adj_seg_kernel(BwdArgs a) {
   int first_frozen = live ? n1 : n0;
   Prop<float, FIELD> pr;
   pr.start(s);
+  pr.init_field(s, a.field, a.field.nodes);
   auto cur = [&]() {
     State<float> q = s;
     q.x = pr.px;

@@ -503,6 +503,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     }
     Prop<R, FIELD> pr;   // fixed steps: current point and the block's increments
     pr.start(st);
+    pr.init_field(st, a.field, nodes);
     if (lane < kTouchWords) touch[lane] = 0u;
     __syncthreads();
 
@@ -550,6 +551,9 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       const int jc = nb / 2;
       if constexpr (MODE == 1) {
         const int step = blk * B;
+        // a checkpoint restarts the adjoint's recompute: the field there is evaluated
+        // at the stored state, as the recompute does
+        if (a.ckpt > 0 && step % a.ckpt == 0) pr.init_field(st, a.field, nodes);
         if (a.tape && in_tile && step % a.ckpt == 0) {
           float* tp = a.tape + (size_t)(step / a.ckpt) * 13 * a.n_pos + gidx;
           const float v13[13] = {(float)st.x, (float)st.y, (float)st.z, (float)st.cx, (float)st.cy, (float)st.cz,
@@ -1115,6 +1119,7 @@ trace_kernel(FieldDev f, double R0, double charge, double hstep, int turn_stop, 
   bool live = true;   // with turn_stop, states after the end of the turn partition stay
   Prop<R, FIELD> pr;  // the scan's propagation, folded every kTraceFold steps
   pr.start(st);
+  pr.init_field(st, f, f.nodes);
   for (int k = 0; k < n_sel; ++k) {
     const int target = steps[k];
     for (; n < target && live; ++n) {

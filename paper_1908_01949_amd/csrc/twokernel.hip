@@ -73,6 +73,7 @@ record_kernel(FieldDev f, const WindowDev* __restrict__ wins, const int64_t* __r
   // blocks of `fold` steps (while the track was live at the block's start)
   Prop<float, FIELD> pr;
   pr.start(st);
+  pr.init_field(st, f, nodes);
   bool live = true, live_blk = true;
   for (int j = 1; j <= n_steps; ++j) {
     if (live) {

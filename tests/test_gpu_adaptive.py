@@ -86,7 +86,10 @@ def test_adaptive_fp64_matches_oracle(rk, geo, ufield, sfield, orc_u, orc_s, kin
 
 def test_adaptive_with_fixed_step_equals_fixed_kernel(rk, geo, sfield):
     """h_min = h_max = 1 mm: the adaptive kernel takes the fixed steps, so its scores
-    equal the fixed-step kernel's to rounding (different block size, same chords)."""
+    equal the fixed-step kernel's to FP32 rounding (same chords; the two round
+    differently: the adaptive step compensates its sums and evaluates every stage's
+    field at every step, the fixed step folds per block and takes the previous last
+    stage's field; each is within ~4e-6 of the oracle's scores, so 1e-5 apart)."""
     ev = synth.event_multi_turn(geo, sfield, 2)
     off, wid, dr = synth.pack_events([ev])
     c = rk.Context(0)
@@ -98,7 +101,7 @@ def test_adaptive_with_fixed_step_equals_fixed_kernel(rk, geo, sfield):
     rk.rkn_scan_windows_adaptive(c.ctx, p, rk.make_adaptive_params(1e-9, 1.0, 1.0), w, a, None,
                                  np.zeros(1, np.int64), np.zeros(1))
     rk.rkn_scan_windows(c.ctx, p, w, b, None, np.zeros(1, np.int64), np.zeros(1))
-    np.testing.assert_allclose(a, b, rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6)
     for bad in (rk.make_adaptive_params(0.0, 0.25, 4.0), rk.make_adaptive_params(1e-5, 4.0, 1.0)):
         with pytest.raises(rk.RknError):
             rk.rkn_scan_windows_adaptive(c.ctx, p, bad, w, a, None, None, None)
