@@ -183,6 +183,21 @@ rkn_status rkn_scan_windows(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_wi
                             const rkn_window *w, double *score, int32_t *n_in,
                             int64_t *best_index, double *best_score);
 
+/* Allocation-free form of rkn_scan_windows, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid it):
+ * the same scan and outputs, which must be device pointers (p->ptr_flags has
+ * RKN_PTR_DEVICE; best_index and best_score are required, score and n_in may be
+ * NULL). Its work memory (device windows, seed tiles, argmin partials, tile counter,
+ * running minima) is one 256 MiB array per GPU, held from the library's load until
+ * the process ends and shared by every call on that GPU: calls on one context's
+ * stream are ordered, calls that overlap on one GPU from other streams race. The
+ * call allocates nothing. RKN_E_CAPACITY when the windows, their tiles and the
+ * running minima of one workgroup do not fit the array; when the minima of a full
+ * persistent grid do not fit, fewer workgroups run. */
+rkn_status rkn_scan_windows_noalloc(rkn_ctx *ctx, const rkn_scan_params *p, int32_t n_windows,
+                                    const rkn_window *w, double *score, int32_t *n_in,
+                                    int64_t *best_index, double *best_score);
+
 /* The work the scan of rkn_scan_windows does on these windows, counted by an
  * instrumented instance of the same kernel (the timed instances carry no counter):
  * counts[0] = seed-steps taken, counts[1] = sphere tests made by the cull (a wire's

@@ -123,6 +123,9 @@ rkn_status rkn_create(int32_t device, void* hip_stream, rkn_ctx** out) {
   if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
       lds_optin > c->max_lds_block)
     c->max_lds_block = lds_optin;
+  // the allocation-free scan's work memory on this device (its absence only disables
+  // that entry point, which then reports the error)
+  (void)rkn::noalloc_init(device);
   if (hip_stream) {
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   } else {
@@ -447,6 +450,20 @@ static rkn_status prepare_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t 
   }
   return RKN_OK;
 }
+
+}  // extern "C"
+
+namespace rkn {
+
+rkn_status prepare_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
+                                std::vector<WindowDev>& wins, std::vector<Tile>& tiles, std::vector<int32_t>& ev_tiles,
+                                int64_t& total) {
+  return prepare_windows(c, p, n_windows, w, wins, tiles, ev_tiles, total, nullptr, nullptr);
+}
+
+}  // namespace rkn
+
+extern "C" {
 
 rkn_status rkn_scan_shape(rkn_ctx* c, const rkn_scan_params* p, int32_t* block_steps, int32_t* seeds_per_tile) {
   if (!c) return RKN_E_ARG;

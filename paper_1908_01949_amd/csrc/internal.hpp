@@ -254,6 +254,27 @@ hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_til
                            int64_t* d_best_i, double* d_best_e, const int32_t* d_ev_tiles, bool alloc_only,
                            const ScanScratch* scratch = nullptr);
 
+// Scan whose work memory the caller provides (no allocation): argmin partials
+// [>= n_tiles], the tile counter, and slab_bytes of slab memory for the running
+// minima (the persistent grid is capped to the workgroup slabs that fit;
+// hipErrorInvalidValue when not even one fits). Tiles and windows already on the
+// device.
+hipError_t launch_scan_raw(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
+                           const WindowDev* d_windows, double* d_score, int32_t* d_nin, int64_t* d_best_i,
+                           double* d_best_e, const int32_t* d_ev_tiles, ArgminPart* d_parts, int* d_counter,
+                           void* d_slab, size_t slab_bytes);
+// Slab bytes one scan workgroup needs for these parameters (block size resolved).
+size_t scan_slab_bytes_per_workgroup(const rkn_ctx* c, const rkn_scan_params* p);
+
+// Windows -> device windows, tiles and per-event tile offsets, validated (api.hip).
+rkn_status prepare_scan_windows(rkn_ctx* c, const rkn_scan_params* p, int32_t n_windows, const rkn_window* w,
+                                std::vector<WindowDev>& wins, std::vector<Tile>& tiles, std::vector<int32_t>& ev_tiles,
+                                int64_t& total);
+
+// Device address of the allocation-free scan's work array on `device`, looked up once
+// per device (noalloc.hip); called by rkn_create with the device current.
+hipError_t noalloc_init(int device);
+
 // Release the rescan loop's buffers (rescan.hip).
 void rescan_release(rkn_ctx* c);
 

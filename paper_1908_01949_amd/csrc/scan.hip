@@ -891,7 +891,8 @@ static int scan_waves(const rkn_ctx* c, int precision, int B) {
 }
 
 template <typename R, int FIELD, int B, int WAVES, int MODE = 0>
-static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only, DevBuf& slab_buf) {
+static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only, DevBuf* slab_buf,
+                                void* raw_slab = nullptr, size_t raw_bytes = 0) {
   constexpr int TILE = 64 * WAVES;
   const int hits_bytes = ((c->max_hits_event * (int)sizeof(HitRec<R>)) + 255) & ~255;
   const int field_bytes = FIELD == 1 ? (((int)padded_field_nodes(c->nr, c->nz) * (int)sizeof(float2)) + 255) & ~255 : 0;
@@ -913,9 +914,18 @@ static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool
   if (grid > max_tiles) grid = max_tiles;
   if (grid < 1) grid = 1;
   a.slab_stride = (int64_t)(c->max_hits_event > 0 ? c->max_hits_event : 1) * TILE;
-  e = slab_buf.ensure((size_t)grid * a.slab_stride * (MODE == 0 ? sizeof(R) : sizeof(unsigned long long)));
-  if (e != hipSuccess) return e;
-  a.mscratch = slab_buf.p;
+  const size_t per_wg = (size_t)a.slab_stride * (MODE == 0 ? sizeof(R) : sizeof(unsigned long long));
+  if (raw_slab) {
+    // caller-provided memory: the persistent grid shrinks to the slabs that fit
+    const int64_t fit = (int64_t)(raw_bytes / per_wg);
+    if (fit < 1) return hipErrorInvalidValue;
+    if (grid > fit) grid = fit;
+    a.mscratch = raw_slab;
+  } else {
+    e = slab_buf->ensure((size_t)grid * per_wg);
+    if (e != hipSuccess) return e;
+    a.mscratch = slab_buf->p;
+  }
   if (alloc_only) return hipSuccess;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, c->stream, a.tile_counter);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(TILE), smem, c->stream, a);
@@ -927,24 +937,24 @@ int scan_tile(const rkn_ctx* c, const rkn_scan_params* p) {
 }
 
 static hipError_t dispatch_scan(rkn_ctx* c, const rkn_scan_params* p, ScanArgs& a, int64_t max_tiles,
-                                bool alloc_only, DevBuf& slab) {
+                                bool alloc_only, DevBuf* slab, void* raw_slab = nullptr, size_t raw_bytes = 0) {
   const int B = resolve_block_steps(c, p);
   if (p->precision == 64)
-    return c->field_kind == 0 ? launch_scan_t<double, 0, 4, 4>(c, a, max_tiles, alloc_only, slab)
-                              : launch_scan_t<double, 1, 4, 4>(c, a, max_tiles, alloc_only, slab);
+    return c->field_kind == 0 ? launch_scan_t<double, 0, 4, 4>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes)
+                              : launch_scan_t<double, 1, 4, 4>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes);
   if (c->field_kind == 0) {
-    if (B == 4) return launch_scan_t<float, 0, 4, 4>(c, a, max_tiles, alloc_only, slab);
-    if (B == 6) return launch_scan_t<float, 0, 6, 4>(c, a, max_tiles, alloc_only, slab);
-    return launch_scan_t<float, 0, 8, 4>(c, a, max_tiles, alloc_only, slab);
+    if (B == 4) return launch_scan_t<float, 0, 4, 4>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes);
+    if (B == 6) return launch_scan_t<float, 0, 6, 4>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes);
+    return launch_scan_t<float, 0, 8, 4>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes);
   }
   const int W = scan_waves(c, 32, B);
   if (B == 4)
-    return W == 16 ? launch_scan_t<float, 1, 4, 16>(c, a, max_tiles, alloc_only, slab)
-                   : launch_scan_t<float, 1, 4, 8>(c, a, max_tiles, alloc_only, slab);
+    return W == 16 ? launch_scan_t<float, 1, 4, 16>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes)
+                   : launch_scan_t<float, 1, 4, 8>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes);
   if (B == 6)
-    return W == 12 ? launch_scan_t<float, 1, 6, 12>(c, a, max_tiles, alloc_only, slab)
-                   : launch_scan_t<float, 1, 6, 8>(c, a, max_tiles, alloc_only, slab);
-  return launch_scan_t<float, 1, 8, 8>(c, a, max_tiles, alloc_only, slab);
+    return W == 12 ? launch_scan_t<float, 1, 6, 12>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes)
+                   : launch_scan_t<float, 1, 6, 8>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes);
+  return launch_scan_t<float, 1, 8, 8>(c, a, max_tiles, alloc_only, slab, raw_slab, raw_bytes);
 }
 
 FieldDev field_dev(const rkn_ctx* c) {
@@ -1006,12 +1016,12 @@ hipError_t launch_refine_fwd(rkn_ctx* c, const rkn_scan_params* p, int64_t n_til
   a.max_hits = c->max_hits_event > 0 ? c->max_hits_event : 1;
   if (n_tiles == 0) return hipSuccess;
   static_assert(kRefineBlock == 8, "the refinement pass runs 8-step blocks");
-  return c->field_kind == 0 ? launch_scan_t<float, 0, 8, 4, 1>(c, a, n_tiles, false, c->r_slab)
-                            : launch_scan_t<float, 1, 8, 8, 1>(c, a, n_tiles, false, c->r_slab);
+  return c->field_kind == 0 ? launch_scan_t<float, 0, 8, 4, 1>(c, a, n_tiles, false, &c->r_slab)
+                            : launch_scan_t<float, 1, 8, 8, 1>(c, a, n_tiles, false, &c->r_slab);
 }
 
 static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_tiles, const WindowDev* d_windows,
-                          double* d_score, int32_t* d_nin, DevBuf& parts, DevBuf& counter) {
+                          double* d_score, int32_t* d_nin, ArgminPart* parts, int* counter) {
   ScanArgs a{};
   a.field = field_dev(c);
   a.hits32 = c->hits32.as<HitRec<float>>();
@@ -1025,7 +1035,7 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
   a.n_layers = c->n_layers;
   a.tiles = d_tiles;
   a.windows = d_windows;
-  a.tile_counter = counter.as<int>();
+  a.tile_counter = counter;
   a.R0 = p->R0;
   a.charge = p->charge;
   a.h = p->step_mm;
@@ -1040,7 +1050,7 @@ static ScanArgs scan_args(rkn_ctx* c, const rkn_scan_params* p, const Tile* d_ti
     a.h_max = (float)c->adapt->h_max_mm;
   }
   a.nin = d_nin;
-  a.parts = parts.as<ArgminPart>();
+  a.parts = parts;
   a.work = c->count_work;
   return a;
 }
@@ -1053,12 +1063,12 @@ hipError_t launch_scan(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, co
   if (e != hipSuccess) return e;
   e = c->counter.ensure(64);
   if (e != hipSuccess) return e;
-  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, c->parts, c->counter);
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, c->parts.as<ArgminPart>(), c->counter.as<int>());
   a.n_tiles = n_tiles;
   a.seeds5 = d_seeds5;
   a.perm = d_perm;
   if (n_tiles > 0) {
-    e = dispatch_scan(c, p, a, n_tiles, false, c->mscratch);
+    e = dispatch_scan(c, p, a, n_tiles, false, &c->mscratch);
     if (e != hipSuccess) return e;
   }
   if (c->n_events > 0) {
@@ -1078,14 +1088,35 @@ hipError_t launch_scan_dev(rkn_ctx* c, const rkn_scan_params* p, int64_t max_til
   if (e != hipSuccess) return e;
   e = s.counter->ensure(64);
   if (e != hipSuccess) return e;
-  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, *s.parts, *s.counter);
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, s.parts->as<ArgminPart>(), s.counter->as<int>());
   a.n_tiles = max_tiles;
   a.n_tiles_dev = d_n_tiles;
-  e = dispatch_scan(c, p, a, max_tiles, alloc_only, *s.slab);
+  e = dispatch_scan(c, p, a, max_tiles, alloc_only, s.slab);
   if (e != hipSuccess || alloc_only) return e;
   hipLaunchKernelGGL(event_argmin_kernel, dim3(c->n_events), dim3(256), 0, c->stream,
                      s.parts->as<ArgminPart>(), d_ev_tiles, d_best_i, d_best_e);
   return hipGetLastError();
+}
+
+hipError_t launch_scan_raw(rkn_ctx* c, const rkn_scan_params* p, int64_t n_tiles, const Tile* d_tiles,
+                           const WindowDev* d_windows, double* d_score, int32_t* d_nin, int64_t* d_best_i,
+                           double* d_best_e, const int32_t* d_ev_tiles, ArgminPart* d_parts, int* d_counter,
+                           void* d_slab, size_t slab_bytes) {
+  ScanArgs a = scan_args(c, p, d_tiles, d_windows, d_score, d_nin, d_parts, d_counter);
+  a.n_tiles = n_tiles;
+  if (n_tiles > 0) {
+    const hipError_t e = dispatch_scan(c, p, a, n_tiles, false, nullptr, d_slab, slab_bytes);
+    if (e != hipSuccess) return e;
+  }
+  if (c->n_events > 0)
+    hipLaunchKernelGGL(event_argmin_kernel, dim3(c->n_events), dim3(256), 0, c->stream, d_parts, d_ev_tiles,
+                       d_best_i, d_best_e);
+  return hipGetLastError();
+}
+
+size_t scan_slab_bytes_per_workgroup(const rkn_ctx* c, const rkn_scan_params* p) {
+  const size_t elem = p->precision == 64 ? sizeof(double) : sizeof(float);
+  return (size_t)(c->max_hits_event > 0 ? c->max_hits_event : 1) * (size_t)scan_tile(c, p) * elem;
 }
 
 // ---------------------------------------------------------------------------------

@@ -126,6 +126,7 @@ _SIGS = {
     "rkn_scan_windows_adaptive": (C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P]),
     "rkn_batch_plan_adaptive": (C.c_int32, [_P, _P, _P, _P]),
     "rkn_rescan_refine": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "rkn_scan_windows_noalloc": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -289,6 +290,14 @@ def rkn_scan_windows(ctx, p: rkn_scan_params, windows, score=None, n_in=None, be
     w = windows_to_c(windows)
     _check(ctx, load_library().rkn_scan_windows(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
                                                 _ptr(best_index), _ptr(best_score)))
+    return score, n_in, best_index, best_score
+
+
+def rkn_scan_windows_noalloc(ctx, p: rkn_scan_params, windows, score, n_in, best_index, best_score):
+    """rkn_scan_windows with no allocation; outputs are device pointers (torch tensors)."""
+    w = windows_to_c(windows)
+    _check(ctx, load_library().rkn_scan_windows_noalloc(ctx, C.byref(p), len(windows), w, _ptr(score), _ptr(n_in),
+                                                        _ptr(best_index), _ptr(best_score)))
     return score, n_in, best_index, best_score
 
 
