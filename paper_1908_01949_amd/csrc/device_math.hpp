@@ -208,12 +208,15 @@ __device__ __forceinline__ void advance(State<R>& st, R dx, R dy, R dz) {
 // scaled by lam (k = t x (lam B)) and r2 = px^2 + py^2 comes from the caller.
 // With the map, b1 (if not NULL) is lam B at p, taken as given instead of evaluated,
 // and b4 (if not NULL) receives lam B at the last stage's point
-// p + h t + h^2/2 k3.
-template <typename R, int FIELD>
+// p + h t + h^2/2 k3, r2_4 (if not NULL) that point's x^2 + y^2.
+// RAW_W (FP32): d[0..2] = k1 + k2 + k3 and d[3..5] = k1 + 2 (k2 + k3) + k4, left for
+// the caller to form the increments h t + h^2/6 d[0..2] and h/6 d[3..5] as
+// multiply-adds into its sums (with the map; the uniform field returns them scaled).
+template <typename R, int FIELD, bool RAW_W = false>
 __device__ __forceinline__ void rkn_delta(const FieldDev& f, const float2* nodes, R lam, R h, R px, R py, R pz,
                                           R tx, R ty, R tz, R r2, R d[6], const R* b1 = nullptr,
-                                          R* b4 = nullptr) {
-  const R h2 = (R)0.5 * h, hh6 = h * h / (R)6, h6 = h / (R)6;
+                                          R* b4 = nullptr, R* r2_4 = nullptr) {
+  const R h2 = (R)0.5 * h, hh6 = h * h / (R)6, h6 = RAW_W ? (R)1 : h / (R)6;
   if constexpr (FIELD == 0) {
     const R a = lam * (R)f.bz;
     const R k1x = a * ty, k1y = -a * tx;
@@ -258,7 +261,9 @@ __device__ __forceinline__ void rkn_delta(const FieldDev& f, const float2* nodes
     const R hh2 = h * h * (R)0.5;
     {
       const R qx = px + h * tx + hh2 * k3x, qy = py + h * ty + hh2 * k3y;
-      field_rz_r2(f, nodes, qx, qy, pz + h * tz + hh2 * k3z, radius2(qx, qy), lam, bx, by, bz);
+      const R r2e = radius2(qx, qy);
+      field_rz_r2(f, nodes, qx, qy, pz + h * tz + hh2 * k3z, r2e, lam, bx, by, bz);
+      if (r2_4) *r2_4 = r2e;
     }
     const R t4x = tx + h * k3x, t4y = ty + h * k3y, t4z = tz + h * k3z;
     const R k4x = t4y * bz - t4z * by;
@@ -269,12 +274,31 @@ __device__ __forceinline__ void rkn_delta(const FieldDev& f, const float2* nodes
       b4[1] = by;
       b4[2] = bz;
     }
-    d[0] = h * tx + hh6 * (k1x + k2x + k3x);
-    d[1] = h * ty + hh6 * (k1y + k2y + k3y);
-    d[2] = h * tz + hh6 * (k1z + k2z + k3z);
-    d[3] = h6 * (k1x + (R)2 * (k2x + k3x) + k4x);
-    d[4] = h6 * (k1y + (R)2 * (k2y + k3y) + k4y);
-    d[5] = h6 * (k1z + (R)2 * (k2z + k3z) + k4z);
+    if constexpr (sizeof(R) == 4 && RAW_W) {
+      // d[0..2] = k1 + (k2 + k3), for the caller's q += h t + h^2/6 d (two multiply-adds)
+      const R sx = k2x + k3x, sy = k2y + k3y, sz = k2z + k3z;
+      d[0] = k1x + sx;
+      d[1] = k1y + sy;
+      d[2] = k1z + sz;
+      d[3] = k1x + (R)2 * sx + k4x;
+      d[4] = k1y + (R)2 * sy + k4y;
+      d[5] = k1z + (R)2 * sz + k4z;
+    } else if constexpr (sizeof(R) == 4) {
+      const R sx = k2x + k3x, sy = k2y + k3y, sz = k2z + k3z;
+      d[0] = h * tx + hh6 * (k1x + sx);
+      d[1] = h * ty + hh6 * (k1y + sy);
+      d[2] = h * tz + hh6 * (k1z + sz);
+      d[3] = h6 * (k1x + (R)2 * sx + k4x);
+      d[4] = h6 * (k1y + (R)2 * sy + k4y);
+      d[5] = h6 * (k1z + (R)2 * sz + k4z);
+    } else {
+      d[0] = h * tx + hh6 * (k1x + k2x + k3x);
+      d[1] = h * ty + hh6 * (k1y + k2y + k3y);
+      d[2] = h * tz + hh6 * (k1z + k2z + k3z);
+      d[3] = h6 * (k1x + (R)2 * (k2x + k3x) + k4x);
+      d[4] = h6 * (k1y + (R)2 * (k2y + k3y) + k4y);
+      d[5] = h6 * (k1z + (R)2 * (k2z + k3z) + k4z);
+    }
   }
 }
 
@@ -316,7 +340,8 @@ struct Prop {
   static constexpr bool kReuse = sizeof(R) == 4 && FIELD == 1;
   R px, py, pz, tx, ty, tz;   // current position and direction
   R qx, qy, qz, ux, uy, uz;   // increments since the block started (FP32)
-  R r2;                       // px^2 + py^2
+  R r2;                       // px^2 + py^2 (FP32 map: of the last stage's point, within
+                              // ~1e-6 mm of p, for the cull's radial range)
   R fb[3];                    // lam B at the current point (FP32 map)
   __device__ __forceinline__ void start(const State<R>& s) {
     px = s.x;
@@ -334,23 +359,35 @@ struct Prop {
   }
   __device__ __forceinline__ void step(const State<R>& s, const FieldDev& f, const float2* nodes, R h) {
     R d[6];
-    rkn_delta<R, FIELD>(f, nodes, s.lam, h, px, py, pz, tx, ty, tz, r2, d, kReuse ? fb : nullptr,
-                        kReuse ? fb : nullptr);
+    constexpr bool kRawW = kReuse;   // FP32 map: the increments as multiply-adds into q, u
+    rkn_delta<R, FIELD, kRawW>(f, nodes, s.lam, h, px, py, pz, tx, ty, tz, r2, d, kReuse ? fb : nullptr,
+                               kReuse ? fb : nullptr, kReuse ? &r2 : nullptr);
     if constexpr (sizeof(R) == 4) {
-      qx += d[0];
-      qy += d[1];
-      qz += d[2];
-      ux += d[3];
-      uy += d[4];
+      const R h6 = h / (R)6, hh6 = h * h / (R)6;
+      if constexpr (FIELD == 1) {
+        qx = __builtin_fmaf(hh6, d[0], __builtin_fmaf(h, tx, qx));
+        qy = __builtin_fmaf(hh6, d[1], __builtin_fmaf(h, ty, qy));
+        qz = __builtin_fmaf(hh6, d[2], __builtin_fmaf(h, tz, qz));
+        ux = __builtin_fmaf(h6, d[3], ux);
+        uy = __builtin_fmaf(h6, d[4], uy);
+      } else {
+        qx += d[0];
+        qy += d[1];
+        qz += d[2];
+        ux += d[3];
+        uy += d[4];
+      }
       px = s.x + qx;
       py = s.y + qy;
       pz = s.z + qz;
       tx = s.tx + ux;
       ty = s.ty + uy;
       if constexpr (FIELD == 1) {
-        uz += d[5];
+        uz = __builtin_fmaf(h6, d[5], uz);
         tz = s.tz + uz;
       }
+      (void)h6;
+      (void)hh6;
     } else {
       px += d[0];
       py += d[1];
@@ -359,7 +396,7 @@ struct Prop {
       ty += d[4];
       if constexpr (FIELD == 1) tz += d[5];
     }
-    r2 = radius2(px, py);
+    if constexpr (!kReuse) r2 = radius2(px, py);
   }
   __device__ __forceinline__ void fold(State<R>& s) {
     if constexpr (sizeof(R) == 4) {

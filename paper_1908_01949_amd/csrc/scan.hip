@@ -346,6 +346,48 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// LDS writes of the wave's lanes visible to all its lanes (list handoffs within a wave).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Dense sphere test of the staged candidates items[lo, hi) (item = (lane << 16) | hit),
+// one per lane: the wire's line against the sphere of radius Kcull + d around the
+// middle point of the owner lane's block (column jc of its points). Survivors are
+// compacted in place from items[lo] on (every lane reads its chunk before any lane
+// writes, and survivors never pass the chunk being read); returns their end.
+template <typename R, bool COUNT>
+__device__ __forceinline__ int test_staged(uint32_t* items, int lo, int hi, const R* pts, const HitRec<R>* s_hits,
+                                           int jc, R Kcull, int lane, int nb, unsigned long long& w_tests,
+                                           unsigned long long& w_chords) {
+  wave_sync();
+  int out = lo;
+  for (int base = lo; base < hi; base += 64) {
+    const bool act = base + lane < hi;
+    const uint32_t it = items[act ? base + lane : lo];
+    wave_sync();
+    const int s = (int)(it >> 16), hh = (int)(it & 0xffffu);
+    const HitRec<R> w = s_hits[hh];
+    const R cx = pts[(jc * 3 + 0) * 64 + s], cy = pts[(jc * 3 + 1) * 64 + s], cz = pts[(jc * 3 + 2) * 64 + s];
+    const R rx = cx - w.mx, ry = cy - w.my, rz = cz - w.mz;
+    const R tt = rx * w.ux + ry * w.uy + rz * w.uz;
+    const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
+    const R thr = Kcull + w.drift;
+    const bool pass = act && (d2 <= thr * thr);
+    if constexpr (COUNT) {
+      w_tests += act ? 1 : 0;
+      w_chords += pass ? nb : 0;
+    }
+    const uint64_t m = __ballot(pass);
+    if (pass) items[out + lane_rank(m)] = it;
+    out += (int)__popcll(m);
+    wave_sync();
+  }
+  return out;
+}
+
 // VAR 0: fixed steps over the whole path; 1: fixed steps, the track ends with its
 // turn partition; 2: adaptive step size (scan mode only), turn_stop as given.
 // COUNT: the instance that also counts its work (seed-steps, sphere tests, chord
@@ -636,12 +678,16 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
       const int b_lo = (int)fminf(fmaxf(rmin, 0.0f), (float)(kTabBins - 1));
       const int b_hi = (int)fminf(fmaxf(rmax, 0.0f), (float)(kTabBins - 1));
       // candidates: per layer whose band meets the block's radial range, the run of
-      // hits that can reach the azimuth sector of the block's middle point; each lane
-      // walks its own runs, hit records gathered from LDS
+      // hits that can reach the azimuth sector of the block's middle point. Each lane
+      // walks its own runs and stages (lane, hit) pairs in the wave's list (cheap
+      // steps, as many as the longest run in the wave); the staged pairs are then
+      // sphere-tested densely, one per lane, and the survivors kept at the list's
+      // front for the distance pass
       const int L0 = s_ltab[b_lo] & 0xff, L1p = s_ltab[b_hi] >> 8;
       const int n_lay = (valid && (!STOP || live0)) ? max(L1p - L0, 0) : 0;
       const float phic = sector_atan2((float)cy, (float)cx);
-      int n_items = 0;
+      int n_items = 0;   // survivors: items[0, n_items)
+      int n_stage = 0;   // staged candidates: items[n_items, n_items + n_stage)
       for (int dl = 0; __ballot(dl < n_lay) != 0; ++dl) {
         const bool has = dl < n_lay;
         const int l = has ? L0 + dl : 0;
@@ -652,25 +698,18 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         const int lb = s_loff[l], nl = s_loff[l + 1] - lb;
         const bool all = ent == kSectAll;
         const int start = all ? 0 : (int)(ent & 511u), cnt = all ? nl : (int)(ent >> 9);
-        for (int k = 0; __ballot(k < cnt) != 0; ++k) {
+        for (int k = 0;; ++k) {
           const bool act = k < cnt;
+          const uint64_t m = __ballot(act);
+          if (m == 0) break;
           int idx = start + k;
           idx -= idx >= nl ? nl : 0;
-          const int hh = act ? lb + idx : 0;
-          const HitRec<R> w = s_hits[hh];
-          const R rx = cx - w.mx, ry = cy - w.my, rz = cz - w.mz;
-          const R tt = rx * w.ux + ry * w.uy + rz * w.uz;
-          const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
-          const R thr = Kcull + w.drift;
-          const bool pass = act && (d2 <= thr * thr);
-          if constexpr (COUNT) {
-            w_tests += act ? 1 : 0;
-            w_chords += pass ? nb : 0;
-          }
-          const uint64_t m = __ballot(pass);
-          if (m) {
-            if (pass) items[n_items + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)hh;
-            n_items += (int)__popcll(m);
+          if (act) items[n_items + n_stage + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)(lb + idx);
+          n_stage += (int)__popcll(m);
+          if (n_items + n_stage > kCap - 64) {
+            n_items = test_staged<R, COUNT>(items, n_items, n_items + n_stage, pts, s_hits, jc, Kcull, lane, nb,
+                                            w_tests, w_chords);
+            n_stage = 0;
             if (n_items > kCap - 64) {
               flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, touch, wave, lane, nb, blk * B,
                                             sqrt_lam);
@@ -679,6 +718,9 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
           }
         }
       }
+      if (n_stage)
+        n_items = test_staged<R, COUNT>(items, n_items, n_items + n_stage, pts, s_hits, jc, Kcull, lane, nb, w_tests,
+                                        w_chords);
       if (n_items)
         flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, touch, wave, lane, nb, blk * B, sqrt_lam);
       if constexpr (COUNT) w_steps += (valid && (!STOP || live0)) ? nb : 0;

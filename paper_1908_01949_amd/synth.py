@@ -613,18 +613,25 @@ def event_fixed_total(geo: Geometry, field: Field, seed: int, n_total: int = 150
 def events_batch(geo: Geometry, field: Field, n_events: int = 512, seed: int = 0,
                  n_steps: int = 6000, sigma: float = 0.2, hits_range=(40, 300),
                  noise_range=(0.1, 0.4), p_range=(60.0, 105.0), max_tracks: int = 3,
-                 pool_size: int = 256, truth_step: float = 1.0) -> list[Event]:
+                 truth_step: float = 1.0) -> list[Event]:
     """Many events: 1-3 e- with p ~ U[60,105] MeV/c, 40-300 hits, 10-40 % noise.
 
-    A pool of accepted truth tracks (reaching the chamber, >= 40 true hits) is traced
-    once, vectorised; each event then draws its tracks from the pool and its hit
-    budget from its own generator.
+    Each event draws its track count and hit budget from its own generator; the
+    tracks are then traced together (vectorised) until every event has its own:
+    no track appears in two events.
     """
     rng = np.random.default_rng([BASE_SEED, 4, seed])
     tf = TruthField(field)
+    plans = []
+    for e in range(n_events):
+        er = np.random.default_rng([BASE_SEED, 4, seed, e])
+        nt = int(er.integers(1, max_tracks + 1))
+        n_total = int(er.integers(hits_range[0], hits_range[1] + 1))
+        plans.append((er, nt, n_total, er.uniform(*noise_range)))
+    need = sum(nt for _, nt, _, _ in plans)
     pool = []
-    while len(pool) < pool_size:
-        k = 2 * pool_size
+    while len(pool) < need:
+        k = 2 * (need - len(pool)) + 8
         pm = rng.uniform(*p_range, k)
         pz = rng.uniform(-25.0, 25.0, k)
         pz = np.clip(pz, -0.5 * pm, 0.5 * pm)
@@ -633,20 +640,18 @@ def events_batch(geo: Geometry, field: Field, n_events: int = 512, seed: int = 0
         pv = np.stack([pt * np.cos(ph), pt * np.sin(ph), pz], -1)
         v = _draw_vertex(rng, k)
         for tr, pmi in zip(trace_truth(tf, v, pv, ELECTRON_Q, n_steps - 20.0, h=truth_step), pm):
-            if tr is None or len(pool) >= pool_size:
+            if tr is None or len(pool) >= need:
                 continue
             w, d, s = true_wire_distances(geo, tr, n_steps - 20.0)
             if w.size >= 40:
                 pool.append((tr.seed, float(pmi), w, d))
     events = []
-    for e in range(n_events):
-        er = np.random.default_rng([BASE_SEED, 4, seed, e])
-        nt = int(er.integers(1, max_tracks + 1))
-        n_total = int(er.integers(hits_range[0], hits_range[1] + 1))
-        f = er.uniform(*noise_range)
+    first = 0
+    for er, nt, n_total, f in plans:
+        picks = range(first, first + nt)
+        first += nt
         n_noise = int(round(f * n_total))
         n_true = n_total - n_noise
-        picks = er.choice(len(pool), size=nt, replace=False)
         # round-robin by arc length across tracks, one hit per wire (smallest distance)
         per = [list(zip(pool[i][2].tolist(), pool[i][3].tolist())) for i in picks]
         chosen: dict[int, tuple[float, int]] = {}

@@ -17,7 +17,7 @@ def rk():
 
 
 def test_batch_matches_oracle_and_replays(rk, geo, sfield, orc_s):
-    evs = synth.events_batch(geo, sfield, 12, seed=1, pool_size=24)
+    evs = synth.events_batch(geo, sfield, 12, seed=1)
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
@@ -97,7 +97,7 @@ def test_batch_block_sizes_agree_and_autotune(rk, geo, sfield):
     block size (and workgroup shape) gives the same scores up to the compiler's choice
     of fused multiply-adds in each instantiation (far inside the oracle tolerance);
     the autotuner leaves the batch planned with one of them."""
-    evs = synth.events_batch(geo, sfield, 10, seed=7, pool_size=20)
+    evs = synth.events_batch(geo, sfield, 10, seed=7)
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)

@@ -248,7 +248,7 @@ def test_refine_argument_and_state_errors(rk, geo, ufield):
 def test_batch_survives_refine_and_larger_eager_scans(rk, geo, sfield):
     """The captured batch graphs keep private scan scratch: refinement and eager scans
     that need more scratch do not disturb a planned batch."""
-    evs = synth.events_batch(geo, sfield, 4, seed=5, pool_size=8)
+    evs = synth.events_batch(geo, sfield, 4, seed=5)
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)

@@ -31,7 +31,7 @@ def rk():
 
 @pytest.fixture(scope="module")
 def batch16(geo, sfield):
-    return synth.events_batch(geo, sfield, n_events=16, seed=3, pool_size=48)
+    return synth.events_batch(geo, sfield, n_events=16, seed=3)
 
 
 def _starts(evs, k, seed=0):

@@ -99,7 +99,7 @@ def test_windows_topk_ties_take_lowest_index(rk, geo, ufield):
 
 
 def test_batch_topk_matches_host_selection(rk, geo, sfield, orc_s):
-    evs = synth.events_batch(geo, sfield, 6, seed=3, pool_size=12)
+    evs = synth.events_batch(geo, sfield, 6, seed=3)
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)

@@ -39,7 +39,7 @@ def _run_both(rk, c, windows, n_events, precision):
 
 @pytest.mark.parametrize("precision", [32, 64])
 def test_noalloc_equals_scan_windows_twice(rk, geo, sfield, precision):
-    evs = synth.events_batch(geo, sfield, 6, seed=5, pool_size=24)
+    evs = synth.events_batch(geo, sfield, 6, seed=5)
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
