@@ -142,3 +142,30 @@ def test_batch_adaptive_equals_window_scan(rk, geo, sfield, orc_s):
     rel = pu.check_scores(score[g], np.array(osc))
     _note(f"adaptive batch: {n} seeds in {len(w)} windows, equal to the window scan, sample rel error {rel:.2e}")
     c.close()
+
+
+def test_adaptive_wide_hough_window_every_seed(rk, geo, sfield, orc_s):
+    """A Hough window of the batch workload (seeds far from any track as well as near
+    it), every seed of a coarser grid over its full span, against the oracle's adaptive
+    score: chords of up to h_max = 4 mm reach wires that the cull must not drop."""
+    from paper_1908_01949_amd import workloads
+    evs = synth.events_batch(geo, sfield, 2, seed=11)
+    off, wid, dr = synth.pack_events(evs)
+    ohp = orc_s.hough_params(b_ref=sfield.b_ref, **workloads.BATCH["hough"])
+    ow = orc_s.hough_seed_windows(ohp, off, wid)
+    w = ow[[0, int(np.nonzero(ow["event"] == 1)[0][0])]].copy()   # one window of each event
+    w["count"] = np.array([3, 4, 3, 3, 4])
+    c = rk.Context(0)
+    c.upload_geometry(geo); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    n = int(sum(int(np.prod(x["count"])) for x in w))
+    p = rk.make_scan_params(n_steps=6000, precision=32)
+    ap = rk.make_adaptive_params(tol_mm=1e-5, h_min_mm=0.25, h_max_mm=4.0)
+    ne = len(evs)
+    sc = np.zeros(n); nin = np.zeros(n, np.int32); bi = np.zeros(ne, np.int64); bs = np.zeros(ne)
+    rk.rkn_scan_windows_adaptive(c.ctx, p, ap, w, sc, nin, bi, bs)
+    osc, onin = _orc_scores(orc_s, orc_s.params(n_steps=6000), oracle.OrcAdaptive(1e-5, 0.25, 4.0), evs, w)
+    rel = pu.check_scores(sc, osc)
+    pu.check_nin(nin, onin, max_frac=0.02)
+    _note(f"wide Hough windows (events {sorted(set(w['event'].tolist()))}): {n} seeds, max rel score error "
+          f"{rel:.2e}, E from {osc.min():.4g} to {osc.max():.4g}")
+    c.close()

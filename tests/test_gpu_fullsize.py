@@ -179,16 +179,23 @@ def test_refine_top8_of_batch_full(rk, batch, orc_s):
         so, mo, phio = orc_s.gn_refine(prm, seeds[q], b["wid"][lo:hi], b["dr"][lo:hi], scale=wl["scale"],
                                        iters=wl["iters"])
         assert phi[q, 0] == pytest.approx(phio[0], rel=1e-3, abs=1e-3)
-        okj, r, _ = orc_s.residual_jacobian(prm, out[q], b["wid"][lo:hi], b["dr"][lo:hi], mo)
+        okj, r, J = orc_s.residual_jacobian(prm, out[q], b["wid"][lo:hi], b["dr"][lo:hi], mo)
         assert okj
         phi_at_gpu = float((r[mo.astype(bool)] ** 2).sum())
         if phi_at_gpu > phio[-1] * (1 + 1e-3) + 1e-3:
-            worse.append((int(q), phi_at_gpu, float(phio[-1])))
-    # from coarse-grid starts far from the minimum, a step-length choice taken at a
-    # near-tie in FP32 vs FP64 can send the two iterations to different basins; allow
-    # that for at most 2 of the 12 sampled seeds and print them
-    print(f"refine: sampled seeds where the oracle's minimum is lower: {worse}", flush=True)
-    assert len(worse) <= 2, worse
+            # from coarse-grid starts far from the minimum, a step-length choice taken
+            # at a near-tie in FP32 vs FP64 can lead the two iterations to different
+            # local minima. The GPU's seed must then be one, by the oracle: at it, with
+            # the same inlier set, the Gauss-Newton model (oracle Jacobian, scaled
+            # variables) predicts a decrease of Phi below 1e-3 of Phi
+            m = mo.astype(bool)
+            JD = J[m] * np.asarray(wl["scale"])
+            delta = np.linalg.lstsq(JD, -r[m], rcond=None)[0]
+            pred = phi_at_gpu - float(((r[m] + JD @ delta) ** 2).sum())
+            worse.append((int(q), round(phi_at_gpu, 4), round(float(phio[-1]), 4), round(pred, 6)))
+            assert pred <= 1e-3 * phi_at_gpu + 1e-4, (int(q), phi_at_gpu, phio[-1], pred)
+    print(f"refine: sampled seeds where the oracle's minimum is lower (seed, Phi at the GPU's seed, oracle's "
+          f"Phi, Gauss-Newton decrease predicted at the GPU's seed): {worse}", flush=True)
 
 
 def test_turn_loop_128_events_sampled(rk, geo, sfield, orc_s):

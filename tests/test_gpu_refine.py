@@ -8,7 +8,15 @@ another eps32 * |p - m| ~ 6e-5 mm; residuals are compared at 1e-3 mm (1/200 of t
 0.2 mm drift resolution). The tangent maps are FP32 per step and accumulated in FP64;
 N = 6000 steps of relative rounding 6e-8 bound the relative error of a derivative by
 N * u * (a few) ~ 1e-3, the bound used for J^T c and J^T J (Frobenius, in the scaled
-variables D = diag(1, 100, 100, 100, 100) that make the columns comparable)."""
+variables D = diag(1, 100, 100, 100, 100) that make the columns comparable).
+
+Where that bound is reached: a residual's gradient row is the unit closest-approach
+vector of its hit, pushed back through the step maps; an FP32 position error dp
+(~1e-4 mm) turns that unit vector by dp / D_i, so hits passing close to their wire
+(small D_i) carry relative row errors of ~1e-4 mm / D_i: 7e-4 at D_i = 0.15 mm. The
+adjoint test prints each kind's worst error beside the smallest inlier D of that
+seed, and checks the tighter bound 5e-4 on seeds whose inlier hits all have
+D_i >= 0.5 mm."""
 import numpy as np
 import pytest
 
@@ -121,11 +129,23 @@ def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind, tur
     cvec = rng.standard_normal((n, H)).astype(np.float32)
     gc = np.zeros((n, 5))
     rk.rkn_adjoint_bwd(c.ctx, cvec, gc, None, None)
-    werr_a = werr_c = werr_g = 0.0
+    # the same with the upstream gradient kept only on hits passing >= 0.5 mm from
+    # their wire: J^T c over rows whose closest-approach direction is well conditioned
+    dfar = np.zeros((n, H), bool)
+    for p in range(n):
+        x = evs[ev[p]]
+        nh = x.wire_id.size
+        dfar[p, :nh] = ~np.isnan(resid[p, :nh]) & (resid[p, :nh] + x.drift >= 0.5)
+    cfar = np.where(dfar, cvec, 0.0).astype(np.float32)
+    gfar = np.zeros((n, 5))
+    rk.rkn_adjoint_bwd(c.ctx, cfar, gfar, None, None)
+    werr_a = werr_c = werr_g = werr_f = 0.0
+    far_worst = 0.0
     for p in range(n):
         x = evs[ev[p]]
         nh = x.wire_id.size
         gm = (~np.isnan(resid[p, :nh])).astype(np.uint8)
+        dmin = float(np.min(resid[p, :nh][gm.astype(bool)] + x.drift[gm.astype(bool)], initial=np.inf))
         ok, r, J = O.residual_jacobian(prm, s5[p], x.wire_id, x.drift, gm)
         assert ok
         JD = J * SCALE
@@ -134,15 +154,24 @@ def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind, tur
         ea = np.linalg.norm(Ag - Ao) / np.linalg.norm(Ao)
         co = JD.T @ np.where(gm.astype(bool), cvec[p, :nh], 0.0)
         ec = np.linalg.norm(gc[p] * SCALE - co) / (np.linalg.norm(JD) * np.linalg.norm(cvec[p, :nh][gm.astype(bool)]))
+        fm = dfar[p, :nh]
+        if fm.any():
+            cf = np.where(fm, cvec[p, :nh], 0.0)
+            ef = np.linalg.norm(gfar[p] * SCALE - JD.T @ cf) / (np.linalg.norm(JD[fm]) * np.linalg.norm(cf[fm]))
+            werr_f = max(werr_f, ef)
         # gradient of Phi: residual differences (<= R_ABS) enter through J^T
         go = 2.0 * JD.T @ np.where(gm.astype(bool), r, 0.0)
         tol_g = DER_REL * np.linalg.norm(go) + 2.0 * np.linalg.norm(JD) * R_ABS * np.sqrt(gm.sum())
         eg = np.linalg.norm(g[p] * SCALE - go)
         werr_a, werr_c, werr_g = max(werr_a, ea), max(werr_c, ec), max(werr_g, eg / tol_g)
-        assert ea < DER_REL, (p, ea)
+        if dmin >= 0.5:
+            far_worst = max(far_worst, ea)
+            assert ea < 0.5 * DER_REL, (p, ea, dmin)
+        assert ea < DER_REL, (p, ea, dmin)
         assert ec < DER_REL, (p, ec)
         assert eg < tol_g, (p, eg, tol_g)
-    print(f"{kind} turn_stop={turn_stop}: J^T J rel {werr_a:.2e}, J^T c rel {werr_c:.2e}, "
+    print(f"{kind} turn_stop={turn_stop}: J^T J rel {werr_a:.2e} (seeds with every inlier D >= 0.5 mm: "
+          f"{far_worst:.2e}), J^T c rel {werr_c:.2e}, J^T c over hits with D >= 0.5 mm rel {werr_f:.2e}, "
           f"grad err/tol {werr_g:.2e}", flush=True)
     c.close()
 
@@ -158,7 +187,25 @@ def test_adjoint_gradient_matches_gpu_finite_differences(rk, geo, ufield, sfield
     off, wid, dr = synth.pack_events(evs)
     c = rk.Context(0)
     c.upload_geometry(geo); c.upload_field(field); c.upload_hits(off, wid, dr)
-    ev, s5 = _seeds(evs, 6, np.random.default_rng(2))
+    # D = |closest-approach vector| is not differentiable at D = 0: the seeds are chosen
+    # beforehand, by the oracle's distances, among candidates around the truth, so that
+    # every inlier of each stays >= 0.15 mm from its wire (the stencil below moves the
+    # trajectory by at most ~0.05 mm)
+    O = _orc(geo, field)
+    prm = O.params(n_steps=2000)
+    cev, cs5 = _seeds(evs, 16, np.random.default_rng(2))
+    keep = []
+    for q in range(cev.size):
+        if sum(1 for k in keep if cev[k] == cev[q]) == 6:
+            continue                      # at most 6 seeds per event
+        x = evs[cev[q]]
+        D = np.sqrt(O.doca2(prm, cs5[q], x.wire_id))
+        inl = (D - x.drift) ** 2 < prm.lambda_mm2
+        if inl.any() and D[inl].min() >= 0.15:
+            keep.append(q)
+    keep = np.array(keep, int)
+    assert keep.size >= 12, keep.size
+    ev, s5 = cev[keep], cs5[keep]
     rk.rkn_refine_setup(c.ctx, rk.make_scan_params(n_steps=2000), ev, s5)
     n, H = ev.size, int(np.diff(off).max())
     resid, _ = _forward(rk, c, n, H)
@@ -174,15 +221,9 @@ def test_adjoint_gradient_matches_gpu_finite_differences(rk, geo, ufield, sfield
     noise = 2.0 * np.nansum(np.abs(resid), axis=1) * 1e-4
     tol = 2e-2 * np.abs(an) + noise
     err = np.abs(fd - an)
-    # D = |closest-approach vector| is not differentiable at D = 0: keep the seeds whose
-    # inlier distances stay away from 0 along the whole difference stencil (which moves
-    # the trajectory by at most ~0.05 mm)
-    dmin = np.array([np.nanmin(resid[p, :evs[ev[p]].wire_id.size] + evs[ev[p]].drift) for p in range(n)])
-    ok = dmin > 0.15
-    print(f"{kind}: {ok.sum()} of {n} seeds with min D > 0.15 mm; FD vs adjoint worst err/tol "
-          f"{np.max((err / tol)[ok]):.2e}, worst rel {np.max((err / np.abs(an))[ok]):.2e}", flush=True)
-    assert ok.sum() >= n // 4
-    assert np.all(err[ok] < tol[ok]), (err, tol, dmin)
+    print(f"{kind}: {n} seeds chosen from {cev.size}; FD vs adjoint worst err/tol {np.max(err / tol):.2e}, "
+          f"worst rel {np.max(err / np.abs(an)):.2e}", flush=True)
+    assert np.all(err < tol), (err, tol)
     c.close()
 
 
