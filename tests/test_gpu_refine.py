@@ -10,13 +10,14 @@ N = 6000 steps of relative rounding 6e-8 bound the relative error of a derivativ
 N * u * (a few) ~ 1e-3, the bound used for J^T c and J^T J (Frobenius, in the scaled
 variables D = diag(1, 100, 100, 100, 100) that make the columns comparable).
 
-Where that bound is reached: a residual's gradient row is the unit closest-approach
-vector of its hit, pushed back through the step maps; an FP32 position error dp
-(~1e-4 mm) turns that unit vector by dp / D_i, so hits passing close to their wire
-(small D_i) carry relative row errors of ~1e-4 mm / D_i: 7e-4 at D_i = 0.15 mm. The
-adjoint test prints each kind's worst error beside the smallest inlier D of that
-seed, and checks the tighter bound 5e-4 on seeds whose inlier hits all have
-D_i >= 0.5 mm."""
+Where that bound is reached: the rows of J carry the tangent maps' FP32 rounding
+accumulated along the path, which grows linearly with the steps a hit lies behind
+(the phase of a helix is linear in its path length): N u = 6000 x 6e-8 = 3.6e-4 for
+the rows of the last hits of a 6000-step multi-turn track, and 2 N u = 7.2e-4 for
+J^T J. Measured: J^T c over hits passing >= 0.5 mm from their wire 3.4e-4, J^T J
+8.3e-4 on the uniform multi-turn events without the turn stop; with the turn stop
+(about a third of the steps) and on the single-turn solenoid events, 1e-5 to 4e-4.
+The 1e-3 bound is 2.8 N u."""
 import numpy as np
 import pytest
 
@@ -140,7 +141,6 @@ def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind, tur
     gfar = np.zeros((n, 5))
     rk.rkn_adjoint_bwd(c.ctx, cfar, gfar, None, None)
     werr_a = werr_c = werr_g = werr_f = 0.0
-    far_worst = 0.0
     for p in range(n):
         x = evs[ev[p]]
         nh = x.wire_id.size
@@ -164,15 +164,13 @@ def test_adjoint_matches_oracle_sensitivities(rk, geo, ufield, sfield, kind, tur
         tol_g = DER_REL * np.linalg.norm(go) + 2.0 * np.linalg.norm(JD) * R_ABS * np.sqrt(gm.sum())
         eg = np.linalg.norm(g[p] * SCALE - go)
         werr_a, werr_c, werr_g = max(werr_a, ea), max(werr_c, ec), max(werr_g, eg / tol_g)
-        if dmin >= 0.5:
-            far_worst = max(far_worst, ea)
-            assert ea < 0.5 * DER_REL, (p, ea, dmin)
         assert ea < DER_REL, (p, ea, dmin)
         assert ec < DER_REL, (p, ec)
         assert eg < tol_g, (p, eg, tol_g)
-    print(f"{kind} turn_stop={turn_stop}: J^T J rel {werr_a:.2e} (seeds with every inlier D >= 0.5 mm: "
-          f"{far_worst:.2e}), J^T c rel {werr_c:.2e}, J^T c over hits with D >= 0.5 mm rel {werr_f:.2e}, "
-          f"grad err/tol {werr_g:.2e}", flush=True)
+    # rounding along the path, not ill-conditioned small-distance rows, sets the error
+    assert werr_f < DER_REL
+    print(f"{kind} turn_stop={turn_stop}: J^T J rel {werr_a:.2e}, J^T c rel {werr_c:.2e}, J^T c over hits with "
+          f"D >= 0.5 mm rel {werr_f:.2e}, grad err/tol {werr_g:.2e}", flush=True)
     c.close()
 
 
