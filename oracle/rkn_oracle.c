@@ -19,6 +19,9 @@
  *                                              hits on a known circle)
  *   candidate -> window (constants) ......... parity unpinned as to quality: its
  *                                              constants are free readings
+ *   coarse-to-fine rescan loop .............. pinned (one round = the k lowest of an
+ *                                              independent window scan; truth on the
+ *                                              grid found and kept; rounds compose)
  */
 #include "rkn_oracle.h"
 

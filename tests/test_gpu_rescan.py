@@ -100,22 +100,23 @@ _ORACLE_RUNS = {}
 
 def _oracle_loop(orc, prm, off, wid, dr, start, step, G, R, target=None):
     """The oracle's loop (cached: both precisions compare against the same runs)."""
-    key = (G, R, None if target is None else target.tobytes())
+    key = (G, R, prm.turn_stop, None if target is None else target.tobytes())
     if key not in _ORACLE_RUNS:
         _ORACLE_RUNS[key] = orc.rescan_refine(prm, off, wid, dr, start, step, grid=G, max_rounds=R, target=target)
     return _ORACLE_RUNS[key]
 
 
-@pytest.mark.parametrize("prec", [64, 32])
-def test_rescan_matches_oracle_loop(rk, geo, sfield, orc_s, batch16, prec):
+@pytest.mark.parametrize("prec,turn_stop", [(64, 0), (32, 0), (64, 1)])
+def test_rescan_matches_oracle_loop(rk, geo, sfield, orc_s, batch16, prec, turn_stop):
     """16 events in the solenoid map, k = 2 kept seeds, 4^5 grids, 3 rounds; then the
-    same with per-event targets that stop events after different rounds."""
+    same with per-event targets that stop events after different rounds. With
+    turn_stop every scored track ends with its turn partition, in both loops."""
     c, off, wid, dr = _ctx(rk, geo, sfield, batch16)
     k, G, R, n_steps = 2, 4, 3, 1500
     start, step = _starts(batch16, k)
-    sp = rk.make_scan_params(n_steps=n_steps, precision=prec)
+    sp = rk.make_scan_params(n_steps=n_steps, precision=prec, turn_stop=turn_stop)
     rp = rk.make_rescan_params(k=k, grid=G, max_rounds=R)
-    prm = orc_s.params(n_steps=n_steps)
+    prm = orc_s.params(n_steps=n_steps, turn_stop=turn_stop)
     rel, abs_, tie = (1e-9, 1e-9, 1e-8) if prec == 64 else (SCORE_REL, SCORE_ABS, None)
     gpu = rk.rkn_rescan_refine(c.ctx, sp, rp, len(batch16), start, step)
     ref = _oracle_loop(orc_s, prm, off, wid, dr, start, step, G, R)
