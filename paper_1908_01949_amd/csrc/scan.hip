@@ -725,7 +725,13 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         flush_items<R, B, TILE, MODE>(items, n_items, pts, s_hits, slab, touch, wave, lane, nb, blk * B, sqrt_lam);
       if constexpr (COUNT) w_steps += (valid && (!STOP || live0)) ? nb : 0;
     }
-    __threadfence();
+    // The minima of a seed were folded by lanes of its own wave, and the slab is this
+    // workgroup's alone: a workgroup-scope release/acquire (the atomics complete at L2;
+    // the reads below bypass L1) orders them before the reads. An agent-scope fence
+    // here would write the whole L2's dirty lines back to memory at every tile.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
     if constexpr (MODE == 1) {
       // ---- refinement outputs: inlier residuals (original hit order), argmin chords
