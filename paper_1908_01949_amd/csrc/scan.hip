@@ -274,8 +274,10 @@ __device__ __forceinline__ void fold_min(S* slab, uint32_t* touch, int hh, int w
 // Dense pass over a wave's work list: item = (lane << 16) | hit. Full groups of 64
 // items take one item per lane and all chords of the block; the remaining n < 64
 // items take G lanes each (G = 8, 4 or 2 with G n <= 64), the chords of an item
-// strided over its lanes and their minimum (distance, then chord) reduced across
-// the G lanes, so the tail pass costs about B / G chords instead of B.
+// strided over its lanes, so the tail pass costs about B / G chords instead of B.
+// Each lane folds the minimum of its own chords: the fold is an atomic minimum of
+// (distance[, chord]) and so order-free, and the seed's running minimum ends as it
+// would after a reduction over the G lanes, without the cross-lane exchange.
 template <typename R, int B, int TILE, int MODE, typename S>
 __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, const R* pts,
                                             const HitRec<R>* s_hits, S* slab, uint32_t* touch, int wave,
@@ -318,25 +320,17 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
     const int s = (int)(it >> 16), hh = (int)(it & 0xffffu);
     const HitRec<R> w = s_hits[hh];
     R dmin = (R)INFINITY;
-    int jmin = 0x7fffffff;
+    int jmin = 0;
     for (int j = sub; j < nb; j += G) {
       const R d2 = seg_wire_d2<R>(pts[(j * 3 + 0) * 64 + s], pts[(j * 3 + 1) * 64 + s], pts[(j * 3 + 2) * 64 + s],
                                   pts[(j * 3 + 3) * 64 + s], pts[(j * 3 + 4) * 64 + s], pts[(j * 3 + 5) * 64 + s],
                                   w.mx, w.my, w.mz, w.ux, w.uy, w.uz, w.L);
-      if (d2 < dmin) {   // chords are visited in increasing order: keeps the lowest on ties
+      if (d2 < dmin) {   // the lane's chords in increasing order: keeps the lowest on ties
         dmin = d2;
         jmin = j;
       }
     }
-    for (int o = 1; o < G; o <<= 1) {
-      const R od = __shfl_xor(dmin, o, 64);
-      const int oj = __shfl_xor(jmin, o, 64);
-      if (od < dmin || (od == dmin && oj < jmin)) {
-        dmin = od;
-        jmin = oj;
-      }
-    }
-    if (act && sub == 0) {
+    if (act && sub < nb) {
       const R lim = w.drift + sqrt_lam;
       fold_min<R, TILE, MODE>(slab, touch, hh, wave, s, dmin, step0 + jmin, lim * lim);
     }
