@@ -35,15 +35,15 @@
 
 namespace rkn {
 
-constexpr int kCap = 192;          // work-list entries per wave
+constexpr int kCap = 176;          // work-list entries per wave
 constexpr int kTabBins = 1024;     // 1 mm radial bins, the last one open-ended
 constexpr float kBandMargin = 1.0f;   // radial band table
 constexpr float kCullMargin = 0.05f;  // sphere test: covers FP32 rounding of the test (~1e-2 mm)
-constexpr int kSectors = 128;         // twisted-azimuth sectors of the candidate table
+constexpr int kSectors = 256;         // twisted-azimuth sectors of the candidate table (finer
+                                      // sectors stage fewer pairs; 256 fill the workgroup's LDS)
 // A sector entry: the run's first hit (bits 0-8) and length (bits 9-15); kSectAll
 // stands for the whole layer (a run longer than 127 hits, or a reach past pi).
 constexpr uint32_t kSectAll = 0xffffu;
-constexpr int kTouchWords = (RKN_MAX_HITS_PER_EVENT + 31) / 32;   // per-wave row bitmap
 constexpr int kTraceFold = 8;   // rkn_trace: steps between folds of the block-relative sums
 constexpr float kPi = 3.14159265358979f;
 
@@ -61,6 +61,7 @@ struct ScanArgs {
   int sect_bytes;             // LDS bytes reserved for the layer x sector table
   int hits_bytes;             // LDS bytes reserved for hit records
   int field_bytes;            // LDS bytes reserved for the field map (0: uniform)
+  int touch_words;            // 32-bit words of a wave's row bitmap (>= max hits / 32)
   const Tile* tiles;
   int64_t n_tiles;
   const int32_t* n_tiles_dev;   // if set, the tile count is read here (captured launches)
@@ -399,12 +400,14 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   uint16_t* s_sect = reinterpret_cast<uint16_t*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2);
   R* s_pts = reinterpret_cast<R*>(smem + a.field_bytes + a.hits_bytes + kTabBins * 2 + a.sect_bytes);
   uint32_t* s_items = reinterpret_cast<uint32_t*>(s_pts + WAVES * (B + 1) * 3 * 64);
-  __shared__ int s_loff[RKN_MAX_LAYERS + 1];
-  __shared__ float s_slope[RKN_MAX_LAYERS];
+  // small tables sized by the uploaded event set: layer offsets and twist slopes of
+  // the current event, the per-wave row bitmaps
+  int* s_loff = reinterpret_cast<int*>(s_items + WAVES * kCap);
+  float* s_slope = reinterpret_cast<float*>(s_loff + a.n_layers + 1);
+  uint32_t* s_touch = reinterpret_cast<uint32_t*>(s_slope + a.n_layers);
   __shared__ int s_tile;
   __shared__ double s_red_e[WAVES];
   __shared__ long long s_red_i[WAVES];
-  __shared__ uint32_t s_touch[WAVES][kTouchWords];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n_tiles = a.n_tiles_dev ? (int64_t)*a.n_tiles_dev : a.n_tiles;
@@ -414,7 +417,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
   R* pts = s_pts + wave * (B + 1) * 3 * 64;
   uint32_t* items = s_items + wave * kCap;
   Slab* slab = reinterpret_cast<Slab*>(a.mscratch) + (size_t)blockIdx.x * a.slab_stride;
-  uint32_t* touch = s_touch[wave];
+  uint32_t* touch = s_touch + wave * a.touch_words;
   unsigned long long w_steps = 0, w_tests = 0, w_chords = 0;   // COUNT only
   // every slab entry holds "no minimum yet" between tiles: written here once, then
   // reset by the tile that read it
@@ -540,7 +543,7 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
     Prop<R, FIELD> pr;   // fixed steps: current point and the block's increments
     pr.start(st);
     pr.init_field(st, a.field, nodes);
-    if (lane < kTouchWords) touch[lane] = 0u;
+    if (lane < a.touch_words) touch[lane] = 0u;
     __syncthreads();
 
     constexpr bool STOP = VAR != 0;    // lanes can end before the last block
@@ -870,17 +873,27 @@ event_argmin_kernel(const ArgminPart* __restrict__ parts, const int32_t* __restr
 }
 
 // LDS bytes of the layer x sector candidate table (uint16 entries, 256-byte rounded).
+static size_t align64(size_t n) { return (n + 63) & ~(size_t)63; }
+
 static size_t sect_table_bytes(const rkn_ctx* c) {
-  return ((size_t)std::max(c->n_layers, 1) * kSectors * sizeof(uint16_t) + 255) & ~(size_t)255;
+  return align64((size_t)std::max(c->n_layers, 1) * kSectors * sizeof(uint16_t));
 }
 
-// LDS bytes of one workgroup of scan_kernel<R, FIELD, B, WAVES, ...>.
+static int touch_words(const rkn_ctx* c) { return std::max((c->max_hits_event + 31) / 32, 1); }
+
+// LDS regions of one workgroup of scan_kernel<R, FIELD, B, WAVES, ...>, in order:
+// field map, hit records, radial table, sector table, points, work lists, layer
+// offsets and slopes, row bitmaps.
+static size_t field_lds_bytes(const rkn_ctx* c, int field) {
+  return field == 1 ? align64(padded_field_nodes(c->nr, c->nz) * sizeof(float2)) : 0;
+}
+static size_t hits_lds_bytes(const rkn_ctx* c, size_t rsize) {
+  return align64((size_t)c->max_hits_event * (rsize == 4 ? sizeof(HitRec<float>) : sizeof(HitRec<double>)));
+}
 static size_t scan_lds_bytes(const rkn_ctx* c, size_t rsize, int field, int B, int waves) {
-  const size_t hits = ((size_t)c->max_hits_event * (rsize == 4 ? sizeof(HitRec<float>) : sizeof(HitRec<double>)) +
-                       255) & ~(size_t)255;
-  const size_t fld = field == 1 ? ((padded_field_nodes(c->nr, c->nz) * sizeof(float2)) + 255) & ~(size_t)255 : 0;
-  return fld + hits + kTabBins * 2 + sect_table_bytes(c) + (size_t)waves * (B + 1) * 3 * 64 * rsize +
-         (size_t)waves * kCap * 4;
+  return field_lds_bytes(c, field) + hits_lds_bytes(c, rsize) + kTabBins * 2 + sect_table_bytes(c) +
+         (size_t)waves * (B + 1) * 3 * 64 * rsize + (size_t)waves * kCap * 4 +
+         (size_t)(2 * std::max(c->n_layers, 1) + 1) * 4 + (size_t)waves * touch_words(c) * 4;
 }
 
 // Steps per block; 0 picks the default: 6 for the FP32 field-map path (12-wave
@@ -936,11 +949,10 @@ template <typename R, int FIELD, int B, int WAVES, int MODE = 0>
 static hipError_t launch_scan_t(rkn_ctx* c, ScanArgs& a, int64_t max_tiles, bool alloc_only, DevBuf* slab_buf,
                                 void* raw_slab = nullptr, size_t raw_bytes = 0) {
   constexpr int TILE = 64 * WAVES;
-  const int hits_bytes = ((c->max_hits_event * (int)sizeof(HitRec<R>)) + 255) & ~255;
-  const int field_bytes = FIELD == 1 ? (((int)padded_field_nodes(c->nr, c->nz) * (int)sizeof(float2)) + 255) & ~255 : 0;
-  a.hits_bytes = hits_bytes;
-  a.field_bytes = field_bytes;
+  a.hits_bytes = (int)hits_lds_bytes(c, sizeof(R));
+  a.field_bytes = (int)field_lds_bytes(c, FIELD);
   a.sect_bytes = (int)sect_table_bytes(c);
+  a.touch_words = touch_words(c);
   const size_t smem = scan_lds_bytes(c, sizeof(R), FIELD, B, WAVES);
   if (smem + 256 > (size_t)c->max_lds_block) return hipErrorInvalidConfiguration;
   auto kern = a.turn_stop ? scan_kernel<R, FIELD, B, WAVES, MODE, 1> : scan_kernel<R, FIELD, B, WAVES, MODE, 0>;
