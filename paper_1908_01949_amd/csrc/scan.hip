@@ -370,7 +370,7 @@ __device__ __forceinline__ int test_staged(uint32_t* items, int lo, int hi, cons
     const R tt = rx * w.ux + ry * w.uy + rz * w.uz;
     const R d2 = rx * rx + ry * ry + rz * rz - tt * tt;
     const R thr = Kcull + w.drift;
-    const bool pass = act && (d2 <= thr * thr);
+    const bool pass = act & (d2 <= thr * thr);   // every lane's loads are in bounds
     if constexpr (COUNT) {
       w_tests += act ? 1 : 0;
       w_chords += pass ? nb : 0;
@@ -695,13 +695,16 @@ __global__ void __launch_bounds__(64 * WAVES) scan_kernel(ScanArgs a) {
         const int lb = s_loff[l], nl = s_loff[l + 1] - lb;
         const bool all = ent == kSectAll;
         const int start = all ? 0 : (int)(ent & 511u), cnt = all ? nl : (int)(ent >> 9);
+        // the run's first item and the step at which it wraps to the layer's first hit,
+        // formed before the loop (so the loop waits on none of the table reads)
+        const uint32_t first = ((uint32_t)lane << 16) | (uint32_t)(lb + start);
+        const int wrap = nl - start;
         for (int k = 0;; ++k) {
           const bool act = k < cnt;
           const uint64_t m = __ballot(act);
           if (m == 0) break;
-          int idx = start + k;
-          idx -= idx >= nl ? nl : 0;
-          if (act) items[n_items + n_stage + lane_rank(m)] = ((uint32_t)lane << 16) | (uint32_t)(lb + idx);
+          const int off = k < wrap ? k : k - nl;
+          if (act) items[n_items + n_stage + lane_rank(m)] = first + (uint32_t)off;
           n_stage += (int)__popcll(m);
           if (n_items + n_stage > kCap - 64) {
             n_items = test_staged<R, COUNT>(items, n_items, n_items + n_stage, pts, s_hits, jc, Kcull, lane, nb,
