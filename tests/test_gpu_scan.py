@@ -451,3 +451,30 @@ def test_work_counts_match_cull_model(rk, geo, ufield, sfield, ctx_u, ctx_s, fie
     assert steps == m_steps == 32 * n_steps
     assert abs(chords - m_chords) <= 0.005 * m_chords + 2 * B
     assert tests >= chords // B > 0
+
+
+@pytest.mark.parametrize("n_layers,tile", [(6, 768), (40, 512)])
+def test_scan_other_layer_counts(rk, sfield, n_layers, tile):
+    """Chambers of 6 and 40 layers in the field map: the per-event layer and sector
+    tables are sized by the geometry (with 40 layers the 12-wave shape no longer fits
+    the LDS and the scan falls back to 8-wave workgroups); scores, n_in and the best
+    seed match the oracle's."""
+    import oracle
+    g = synth.make_geometry(n_layers=n_layers)
+    evs = synth.events_batch(g, sfield, 1, seed=21, hits_range=(8, 480))
+    off, wid, dr = synth.pack_events(evs)
+    c = rk.Context(0)
+    c.upload_geometry(g); c.upload_field(sfield); c.upload_hits(off, wid, dr)
+    w = synth.make_windows([(0, 0, evs[0].truth_seeds[0], [0.03, 20, 3, 3, 3], [3, 4, 3, 3, 4])])
+    p = rk.make_scan_params(n_steps=3000, precision=32)
+    assert rk.rkn_scan_shape(c.ctx, p) == (6, tile)
+    n = int(np.prod(w[0]["count"]))
+    score = np.zeros(n); nin = np.zeros(n, np.int32); bi = np.zeros(1, np.int64); bs = np.zeros(1)
+    rk.rkn_scan_windows(c.ctx, p, w, score, nin, bi, bs)
+    c.close()
+    O = oracle.Oracle(g, sfield)
+    osc, onin, obi, obs, _ = O.scan_windows(O.params(n_steps=3000), off, wid, dr, w)
+    rel = pu.check_scores(score, osc)
+    pu.check_nin(nin, onin)
+    pu.check_best(bi[0], osc)
+    _note(f"{n_layers} layers, {wid.size} hits, tile {tile}: {n} seeds, max rel score error {rel:.2e}")
