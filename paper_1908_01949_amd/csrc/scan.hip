@@ -276,9 +276,11 @@ __device__ __forceinline__ void fold_min(S* slab, uint32_t* touch, int hh, int w
 // items take one item per lane and all chords of the block; the remaining n < 64
 // items take G lanes each (G = 8, 4 or 2 with G n <= 64), the chords of an item
 // strided over its lanes, so the tail pass costs about B / G chords instead of B.
-// Each lane folds the minimum of its own chords: the fold is an atomic minimum of
-// (distance[, chord]) and so order-free, and the seed's running minimum ends as it
-// would after a reduction over the G lanes, without the cross-lane exchange.
+// The fold is an atomic minimum of (distance[, chord]) and so order-free: lanes of an
+// item may fold separately and the seed's running minimum ends as after a full
+// reduction over the G lanes. In the scan, adjacent lanes first merge their minima
+// with one row shift (half the atomics, and half their L2 write-backs, for three
+// instructions); the refinement pass folds every lane's (distance, chord) key.
 template <typename R, int B, int TILE, int MODE, typename S>
 __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, const R* pts,
                                             const HitRec<R>* s_hits, S* slab, uint32_t* touch, int wave,
@@ -331,7 +333,18 @@ __device__ __forceinline__ void flush_items(const uint32_t* items, int n_items, 
         jmin = j;
       }
     }
-    if (act && sub < nb) {
+    bool folds = act && sub < nb;
+    if constexpr (MODE == 0 && sizeof(R) == 4) {
+      if (G > 1) {
+        // pairs of an item's lanes (aligned inside rows of 16) merge their minima first:
+        // non-negative floats order as their bit patterns
+        const unsigned bits = __float_as_uint(dmin);
+        const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)bits, (int)bits, 0x101, 0xf, 0xf, false);
+        dmin = __uint_as_float(o < bits ? o : bits);
+        folds = folds && (sub & 1) == 0;
+      }
+    }
+    if (folds) {
       const R lim = w.drift + sqrt_lam;
       fold_min<R, TILE, MODE>(slab, touch, hh, wave, s, dmin, step0 + jmin, lim * lim);
     }
