@@ -490,6 +490,7 @@ def main():
     achieved = f_alg * seed_steps / (np.mean(ms_s) * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=flops.PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / flops.PEAK_FP32_TFLOPS, 4), traffic=measured_traffic(),
+                frac_unpacked_fp32=round(achieved / flops.PEAK_FP32_UNPACKED_TFLOPS, 4),
                 flops_per_seed_step=round(f_alg, 2), q_kernel=round(q_kernel, 5),
                 sphere_tests_per_seed_step=round(k_tests / k_steps, 5),
                 kernel=f"scan_kernel<float, rz field, {bsteps}-step blocks, {bwaves} waves>")

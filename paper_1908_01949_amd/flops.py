@@ -24,9 +24,11 @@ F_FIELD = 31
 F_RKN_GRID = 127 + 3 * F_FIELD
 F_DOCA = 50
 
-# MI355X vector peaks (dense, per the vendor): FP32 with packed math, FP64.
+# MI355X vector peaks (dense, per the vendor): FP32 with packed math, FP64; and the
+# FP32 rate without packed math (one FMA per lane per clock), the kernels' ceiling here.
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 
 
 def per_seed_step(field_kind: str, pairs_per_step: float) -> float:
